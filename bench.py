@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the multigrid GPW hot path on one MI355X.
+
+One step = eval_rho (density matrix -> rho on every level) + eval_mat (level
+potentials -> matrix) of the 256-water-like system (config-5 member with 256
+water units: 768 atoms, 10496 Cartesian AOs, levels 400/130/45/15 Ry, mesh
+192^3/108^3/64^3/40^3, tau = 1e-6), FP64, inputs resident in HBM.
+
+Prints ONE JSON line.  ``value`` is GFLOP/s of rho+mat counted with the
+per-(pair image, grid point) flop model over the points inside every pair
+image's truncation sphere (the algorithmic work, independent of blocking).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12      # MI355X FP64 vector FMA peak: 256 CU x 128 flop/clk x 2.4 GHz
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="water256", choices=["water256", "c2", "c3", "c4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-atoms", type=int, default=0, help="atoms in the oracle sample (0 = auto)")
+    ap.add_argument("--extras", type=int, default=1, help="also time grad, fp32 and the plan")
+    return ap.parse_args()
+
+
+def make_system(name):
+    from paper_2603_24881_amd import synth
+    if name == "water256":
+        return synth.water256(), "water256: 256 water-like units, L=29.53 bohr, 768 atoms, 10496 AOs, O 3s2p2d1f / H 2s1p"
+    s = synth.CONFIGS[name]()
+    return s, f"{name}: {s.natm} atoms, {s.n_ao} AOs"
+
+
+def timed(fn, steps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3 / steps
+
+
+def cpu_baseline(system, D_np, V_np, natoms_hint):
+    """The oracle on a bounded sample: pairs whose first primitive sits on the
+    first ``n`` atoms; rho and mat; GFLOP/s with the same per-point flop model
+    (ordered pairs, points inside the sphere)."""
+    import oracle
+    n = natoms_hint or max(3, int(round(system.natm * 0.02)))
+    mask = np.zeros(system.natm, dtype=np.uint8)
+    mask[:n] = 1
+    o = oracle.Oracle(system, atom_mask=mask)
+    t0 = time.perf_counter()
+    o.rho(D_np)
+    t1 = time.perf_counter()
+    c_rho = o.counts.copy()
+    o.mat(V_np)
+    t2 = time.perf_counter()
+    c_mat = o.counts.copy()
+    flops = 0.0
+    for la in range(4):
+        for lb in range(4):
+            na, nb = (la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2
+            f = 2 * na * nb + 2 * (na + nb) + 4
+            flops += f * (c_rho[4 * la + lb] + c_mat[4 * la + lb])
+    secs = t2 - t0
+    return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle eval_rho+eval_mat over the pair images whose first primitive sits on the "
+                      f"first {n} of {system.natm} atoms ({secs:.1f} s, {flops:.3e} flops)",
+            "seconds": secs, "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+                                   "(the path shards by grid blocks, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    from paper_2603_24881_amd import synth
+    from paper_2603_24881_amd.gpw import GPW
+
+    dev = torch.device("cuda", 0)
+    system, desc = make_system(args.workload)
+    log(f"[bench] {desc}")
+    t0 = time.perf_counter()
+    g = GPW(system)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = g.info
+    log(f"[bench] plan {plan_s:.2f} s, pairs {sum(info['n_pairs'])}, incidences {sum(info['n_incidences'])}, "
+        f"mesh {info['mesh']}, device bytes {info['device_bytes'] / 1e9:.2f} GB")
+    C = synth.draw_orbitals(system)
+    Cd = torch.as_tensor(C, device=dev)
+    D = (Cd @ Cd.T).contiguous()
+    del Cd
+    V_np = synth.make_potentials(info["mesh"], system.seed)
+    V = [torch.as_tensor(v, device=dev).contiguous() for v in V_np]
+    rho = g.new_grids()
+    M = torch.empty((g.n_ao, g.n_ao), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        g.rho(D, out=rho)
+        g.mat(V, out=M)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_step = timed(step, args.steps, stream)
+    t_rho = timed(lambda: g.rho(D, out=rho), max(2, args.steps // 2), stream)
+    t_mat = timed(lambda: g.mat(V, out=M), max(2, args.steps // 2), stream)
+    f_rho_s, f_mat_s = info["flops_rho_sphere"], info["flops_mat_sphere"]
+    f_rho_b, f_mat_b = info["flops_rho_block"], info["flops_mat_block"]
+    value = (f_rho_s + f_mat_s) / t_step / 1e9
+    log(f"[bench] step {t_step * 1e3:.2f} ms (rho {t_rho * 1e3:.2f} ms, mat {t_mat * 1e3:.2f} ms), "
+        f"{value:.0f} GFLOP/s algorithmic")
+    if t_rho >= t_mat:
+        dom, dt, fl = "k_rho (density collocation, all classes and levels of one eval_rho)", t_rho, f_rho_s
+    else:
+        dom, dt, fl = "k_mat (potential integration, all classes and levels of one eval_mat)", t_mat, f_mat_s
+    out = {
+        "metric": "eval_rho+eval_mat FP64 GFLOP/s & %peak; served requests/s + p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "tau": system.tau, "levels_ry": system.ke_cutoff_ry,
+                   "mesh": info["mesh"], "rel_cutoff_ry": system.rel_cutoff_ry},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": round(fl / dt / 1e12, 3),
+                     "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": round(fl / dt / PEAK_FP64, 4),
+                     "traffic": None},
+        "pct_fp64_peak": round(100 * value * 1e9 / PEAK_FP64, 2),
+        "ms_rho": round(t_rho * 1e3, 4),
+        "ms_mat": round(t_mat * 1e3, 4),
+        "block_gflops": round((f_rho_b + f_mat_b) / t_step / 1e9, 2),
+        "plan_s": round(plan_s, 3),
+        "n_pair_images": int(sum(info["n_pairs"])),
+        "n_block_incidences": int(sum(info["n_incidences"])),
+    }
+    if args.extras:
+        G = torch.empty((g.natm, 3), dtype=torch.float64, device=dev)
+        g.grad(D, V, out=G)
+        t_grad = timed(lambda: g.grad(D, V, out=G), max(2, args.steps // 2), stream)
+        out["ms_grad"] = round(t_grad * 1e3, 4)
+        out["grad_gflops"] = round(info["flops_grad_sphere"] / t_grad / 1e9, 2)
+        log(f"[bench] grad {t_grad * 1e3:.2f} ms")
+        g32 = GPW(system, precision="fp32")
+        g32.rho(D, out=rho)
+        g32.mat(V, out=M)
+        t32 = timed(lambda: (g32.rho(D, out=rho), g32.mat(V, out=M)), max(2, args.steps // 2), stream)
+        out["ms_step_fp32"] = round(t32 * 1e3, 4)
+        log(f"[bench] fp32 step {t32 * 1e3:.2f} ms")
+        g32.close()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)...")
+        Dn = D.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(system, Dn, V_np, args.cpu_atoms)
+        log(f"[bench] cpu {out['cpu_baseline']['value']:.2f} GFLOP/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

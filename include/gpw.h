@@ -1,0 +1,197 @@
+/*
+ * gpw.h - C ABI of the MI355X (gfx950) multigrid Gaussian-plane-wave
+ * collocation / integration library.
+ *
+ * The library evaluates, on one GPU, the three kernels of the multigrid FFTDF
+ * Fock build and nuclear gradient described in "Implementation of the
+ * multigrid Gaussian-Plane-Wave algorithm with GPU acceleration in PySCF"
+ * (arXiv 2603.24881):
+ *
+ *   gpw_eval_rho   density matrix D -> rho_l(r) on every multigrid level
+ *                  (Sec. II, Eq. (rho); Sec. III.A, Eq. (rho_wrap); Alg. 1)
+ *   gpw_eval_mat   level potentials v_l(r) -> matrix M_{mu nu}
+ *                  (Sec. II, Eq. (J); Sec. III.A, Eq. (J_wrap); Alg. 2)
+ *   gpw_eval_grad  D, v_l -> dE/dR_A of E = sum_l w_l <v_l, rho_l>
+ *                  (Sec. III.B, Alg. 3)
+ *
+ * behind a plan (gpw_plan) that screens primitive Gaussian pairs and maps them
+ * to grid blocks (Sec. III.B and the appendix on GTO screening, Algs. 4, 5).
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * Units: bohr, bohr^-2 for exponents, Rydberg for plane-wave cutoffs.
+ * Cell: orthorhombic; lattice vectors are the rows of a[3][3] and must be
+ *   diagonal (non-orthogonal cells return GPW_EUNSUPPORTED).
+ * Basis: contracted Cartesian shells, l = 0..3.  exps/coefs are the primitive
+ *   exponents and raw coefficients: a contracted AO is
+ *   sum_k coefs[k] (x-Ax)^i (y-Ay)^j (z-Az)^k exp(-exps[k] |r-A|^2)
+ *   (un-normalised Cartesian primitives, Sec. III.A, Eq. (gx)).
+ * AO order: shells in input order; inside a shell the Cartesian components in
+ *   lexicographic order (lx descending, then ly descending): s; x y z;
+ *   xx xy xz yy yz zz; xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz.
+ * Matrices: n_ao x n_ao, row-major, FP64, device memory.
+ * Grids: level l holds mesh[l][0]*mesh[l][1]*mesh[l][2] FP64 values in C
+ *   order [i0][i1][i2]; point (i0,i1,i2) sits at (i0 h0, i1 h1, i2 h2) with
+ *   h_d = L_d / mesh[l][d] (origin at the cell corner).
+ * Quadrature weight of level l: w_l = Omega / N_l (Sec. III.A, the weight in
+ *   the definition of the V tensor).  eval_mat and eval_grad apply it; rho is
+ *   unweighted.
+ * Truncation: a primitive pair image p (exponents a, b; centres A, B + T)
+ *   with alpha_p = a + b, P = (a A + b (B+T)) / alpha_p, L = l_a + l_b and
+ *   K = c_a c_b exp(-a b / alpha_p |A - B - T|^2) is dropped when the maximum
+ *   of f(r) = |K| r^(L+2) exp(-alpha_p r^2) is below tau; otherwise it
+ *   contributes at the grid points with |r - P| <= R, f(R) = tau, R beyond the
+ *   maximum (Sec. III.A, Eq. (cut) and the sphere about P used with
+ *   Eq. (exp_rr)).
+ * Levels: a pair image goes to the coarsest level i with
+ *   ke_cutoff_ry[i] >= alpha_p * rel_cutoff_ry, or to level 0 (finest) when
+ *   none qualifies (Sec. II, multigrid).  Default mesh of a level: per axis the
+ *   smallest 2,3,5-smooth N >= sqrt(E) L / pi.
+ *
+ * Errors: every call returns a gpw_status.  Argument errors are detected
+ * before anything is enqueued.  A device fault surfaces as GPW_EDEVICE on a
+ * later call.  On error the outputs are unspecified and the plan stays valid.
+ * gpw_last_error() returns a thread-local message for the last failure.
+ *
+ * Streams: eval calls enqueue on the given hipStream_t (NULL = the default
+ * stream) and return without synchronising.  Inputs must stay valid and
+ * outputs untouched until the stream reaches the end of the call.  One plan
+ * may serve several streams concurrently when their outputs differ.
+ */
+#ifndef GPW_H
+#define GPW_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPW_MAX_LEVELS 8
+#define GPW_NCLASS 10   /* (l_a, l_b) with 3 >= l_a >= l_b >= 0 */
+
+typedef enum {
+    GPW_OK = 0,
+    GPW_EINVAL = 1,        /* bad argument (NULL pointer, l > 3, exponent <= 0, ...) */
+    GPW_EUNSUPPORTED = 2,  /* valid but not implemented (non-orthogonal cell, g shells) */
+    GPW_ENOMEM = 3,        /* device allocation failed */
+    GPW_EDEVICE = 4,       /* HIP runtime error or device fault */
+    GPW_EBUDGET = 5        /* the request does not fit the caller's memory budget */
+} gpw_status;
+
+typedef enum { GPW_FP64 = 0, GPW_FP32 = 1 } gpw_precision;
+
+typedef struct gpw_plan_s *gpw_plan_t;
+
+typedef struct {
+    double a[3][3];        /* lattice vectors as rows (bohr); must be diagonal */
+} gpw_cell;
+
+typedef struct {
+    int natm;
+    const double *coords;       /* natm*3, any position (not wrapped) */
+    int nshell;
+    const int *shell_atom;      /* nshell, atom index of each shell */
+    const int *shell_l;         /* nshell, 0..3 */
+    const int *shell_nprim;     /* nshell, >= 1 */
+    const int *shell_prim0;     /* nshell, offset of the shell's primitives */
+    const double *exps;         /* primitive exponents, > 0 */
+    const double *coefs;        /* raw primitive coefficients */
+} gpw_basis;
+
+typedef struct {
+    int nlevels;                /* 1..GPW_MAX_LEVELS */
+    const double *ke_cutoff_ry; /* nlevels, strictly descending; may be NULL when nlevels == 1
+                                   and mesh is given */
+    const int *mesh;            /* optional nlevels*3 mesh override (NULL = mesh rule) */
+    double rel_cutoff_ry;       /* E_rel of the level rule */
+    double tau;                 /* screening threshold (> 0), e.g. 1e-6 */
+    int precision;              /* gpw_precision of the per-point arithmetic */
+    int device;                 /* HIP device ordinal */
+} gpw_cutoffs;
+
+typedef struct {
+    int nlevels;
+    int mesh[GPW_MAX_LEVELS][3];
+    double weight[GPW_MAX_LEVELS];            /* w_l = Omega / N_l */
+    long long n_grid[GPW_MAX_LEVELS];         /* points per level */
+    int n_ao;
+    int natm;
+    int precision;
+    long long n_pairs[GPW_MAX_LEVELS];        /* canonical pair images per level */
+    long long n_pairs_class[GPW_NCLASS];      /* canonical pair images per (l_a, l_b) class */
+    long long n_incidences[GPW_MAX_LEVELS];   /* (pair image, 4^3 block) incidences */
+    long long n_incidences_class[GPW_NCLASS];
+    double sphere_points;                     /* sum over pair images of points inside the sphere */
+    /* flop model (FMA = 2): per (pair image, point), with n_a, n_b the Cartesian counts,
+       F_rho = F_mat = 2 n_a n_b + 2 (n_a + n_b) + 4, F_grad = 4 n_a n_b + 8 (n_a + n_b) + 4.
+       "block" counts 64 points per (pair image, 4^3 block) incidence (the work the
+       grid-block kernels perform); "sphere" counts only points inside the sphere. */
+    double flops_rho_block, flops_rho_sphere;
+    double flops_mat_block, flops_mat_sphere;
+    double flops_grad_block, flops_grad_sphere;
+    long long device_bytes;                   /* device memory held by the plan */
+    int max_box_width;                        /* widest bounding box (points per axis) */
+} gpw_plan_info;
+
+/* Build a plan: screen primitive pair images, assign levels, compute their
+ * truncation spheres, and map them to 4x4x4 grid blocks of each level
+ * (Sec. III.B; appendix on GTO screening, Algs. 4 and 5).  All host inputs
+ * are copied; the caller may free them on return.  The plan owns its device
+ * memory on cut->device.  Synchronous.  Errors: GPW_EINVAL for NULL or invalid
+ * arguments, GPW_EUNSUPPORTED for a non-diagonal cell or l > 3, GPW_ENOMEM,
+ * GPW_EDEVICE. */
+gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis,
+                    const gpw_cutoffs *cut, gpw_plan_t *out);
+
+/* Free a plan and its device memory (NULL is accepted).  The caller must make
+ * sure no enqueued call still uses it. */
+gpw_status gpw_plan_destroy(gpw_plan_t plan);
+
+/* Sizes, meshes, weights, work counts and the flop model of a plan. */
+gpw_status gpw_plan_query(gpw_plan_t plan, gpw_plan_info *out);
+
+/* Density collocation (Sec. II, Eq. (rho); Sec. III.A, Eq. (rho_wrap);
+ * Alg. 1).  D: device, n_ao x n_ao row-major; only (D + D^T)/2 is used.
+ * rho: host array of nlevels device pointers; rho[l] receives the level-l
+ * partial density (overwritten, unweighted).  Enqueued on stream. */
+gpw_status gpw_eval_rho(gpw_plan_t plan, const double *D, double *const *rho, void *stream);
+
+/* Potential integration (Sec. II, Eq. (J); Sec. III.A, Eq. (J_wrap); Alg. 2):
+ * M_{mu nu} = sum_l w_l sum_r v_l(r) sum_{pair images p of (mu, nu)}
+ * Lambda_p,mu nu(r), contracted Cartesian basis, full symmetric matrix.
+ * v: host array of nlevels device pointers to the level potentials.
+ * M: device n_ao x n_ao, overwritten.  Enqueued on stream. */
+gpw_status gpw_eval_mat(gpw_plan_t plan, const double *const *v, double *M, void *stream);
+
+/* Nuclear gradient of the collocation (Sec. III.B, Alg. 3):
+ * grad[A][x] = d/dR_{A,x} sum_l w_l <v_l, rho_l(D; R)> at fixed D and v
+ * (the force is -grad).  D as in gpw_eval_rho, v as in gpw_eval_mat;
+ * grad: device natm x 3, overwritten.  Enqueued on stream. */
+gpw_status gpw_eval_grad(gpw_plan_t plan, const double *D, const double *const *v,
+                         double *grad, void *stream);
+
+/* One task of a batched launch. */
+typedef enum { GPW_OP_RHO = 0, GPW_OP_MAT = 1, GPW_OP_GRAD = 2 } gpw_op;
+
+typedef struct {
+    gpw_plan_t plan;
+    int op;                      /* gpw_op */
+    const double *D;             /* RHO, GRAD */
+    const double *const *v;      /* MAT, GRAD: host array of nlevels device pointers */
+    double *const *rho;          /* RHO: host array of nlevels device pointers */
+    double *out;                 /* MAT: M (n_ao x n_ao); GRAD: natm x 3 */
+} gpw_task;
+
+/* Batched evaluation for serving: the tasks, possibly of different plans, run
+ * as one set of persistent launches that pull work items from a shared queue,
+ * so that the work of several requests overlaps on the device.  Each task
+ * computes exactly what the corresponding single call computes.  Outputs of
+ * different tasks must not overlap.  Enqueued on stream. */
+gpw_status gpw_eval_batch(const gpw_task *tasks, int ntasks, void *stream);
+
+/* Thread-local message describing the last failure in this thread. */
+const char *gpw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPW_H */

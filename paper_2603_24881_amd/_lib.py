@@ -1,0 +1,294 @@
+"""ctypes binding of libgpw (include/gpw.h).
+
+Argument marshalling only: every computation happens in the HIP kernels of
+libgpw.so.  Device buffers are torch tensors (float64, contiguous, on the plan's
+device); streams are torch streams (``torch.cuda.current_stream()`` when not
+given).  If the library has not been built, importing the binding raises:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpw.so")
+
+GPW_MAX_LEVELS = 8
+GPW_NCLASS = 10
+GPW_FP64, GPW_FP32 = 0, 1
+GPW_OP_RHO, GPW_OP_MAT, GPW_OP_GRAD = 0, 1, 2
+STATUS = {0: "GPW_OK", 1: "GPW_EINVAL", 2: "GPW_EUNSUPPORTED", 3: "GPW_ENOMEM",
+          4: "GPW_EDEVICE", 5: "GPW_EBUDGET"}
+
+
+class GPWError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class gpw_cell(C.Structure):
+    _fields_ = [("a", (C.c_double * 3) * 3)]
+
+
+class gpw_basis(C.Structure):
+    _fields_ = [
+        ("natm", C.c_int),
+        ("coords", C.POINTER(C.c_double)),
+        ("nshell", C.c_int),
+        ("shell_atom", C.POINTER(C.c_int)),
+        ("shell_l", C.POINTER(C.c_int)),
+        ("shell_nprim", C.POINTER(C.c_int)),
+        ("shell_prim0", C.POINTER(C.c_int)),
+        ("exps", C.POINTER(C.c_double)),
+        ("coefs", C.POINTER(C.c_double)),
+    ]
+
+
+class gpw_cutoffs(C.Structure):
+    _fields_ = [
+        ("nlevels", C.c_int),
+        ("ke_cutoff_ry", C.POINTER(C.c_double)),
+        ("mesh", C.POINTER(C.c_int)),
+        ("rel_cutoff_ry", C.c_double),
+        ("tau", C.c_double),
+        ("precision", C.c_int),
+        ("device", C.c_int),
+    ]
+
+
+class gpw_plan_info(C.Structure):
+    _fields_ = [
+        ("nlevels", C.c_int),
+        ("mesh", (C.c_int * 3) * GPW_MAX_LEVELS),
+        ("weight", C.c_double * GPW_MAX_LEVELS),
+        ("n_grid", C.c_longlong * GPW_MAX_LEVELS),
+        ("n_ao", C.c_int),
+        ("natm", C.c_int),
+        ("precision", C.c_int),
+        ("n_pairs", C.c_longlong * GPW_MAX_LEVELS),
+        ("n_pairs_class", C.c_longlong * GPW_NCLASS),
+        ("n_incidences", C.c_longlong * GPW_MAX_LEVELS),
+        ("n_incidences_class", C.c_longlong * GPW_NCLASS),
+        ("sphere_points", C.c_double),
+        ("flops_rho_block", C.c_double),
+        ("flops_rho_sphere", C.c_double),
+        ("flops_mat_block", C.c_double),
+        ("flops_mat_sphere", C.c_double),
+        ("flops_grad_block", C.c_double),
+        ("flops_grad_sphere", C.c_double),
+        ("device_bytes", C.c_longlong),
+        ("max_box_width", C.c_int),
+    ]
+
+
+class gpw_task(C.Structure):
+    _fields_ = [
+        ("plan", C.c_void_p),
+        ("op", C.c_int),
+        ("D", C.c_void_p),
+        ("v", C.c_void_p),
+        ("rho", C.c_void_p),
+        ("out", C.c_void_p),
+    ]
+
+
+EXPORTS = ("gpw_plan", "gpw_plan_destroy", "gpw_plan_query", "gpw_eval_rho", "gpw_eval_mat",
+           "gpw_eval_grad", "gpw_eval_batch", "gpw_last_error")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgpw.so; raises if it is missing (build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libgpw.so not built at {path}; run `python -m paper_2603_24881_amd.build`")
+    lib = C.CDLL(path)
+    lib.gpw_plan.argtypes = [C.POINTER(gpw_cell), C.POINTER(gpw_basis), C.POINTER(gpw_cutoffs),
+                             C.POINTER(C.c_void_p)]
+    lib.gpw_plan_destroy.argtypes = [C.c_void_p]
+    lib.gpw_plan_query.argtypes = [C.c_void_p, C.POINTER(gpw_plan_info)]
+    lib.gpw_eval_rho.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_eval_mat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_eval_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_eval_batch.argtypes = [C.POINTER(gpw_task), C.c_int, C.c_void_p]
+    lib.gpw_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name != "gpw_last_error":
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise GPWError(status, load().gpw_last_error().decode())
+
+
+def _ptr_array(ptrs):
+    arr = (C.c_void_p * max(1, len(ptrs)))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p
+    return arr
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, what):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{what}: expected a contiguous float64 device tensor")
+    return t.data_ptr()
+
+
+class PlanHandle:
+    """Owns a gpw_plan_t; the host arrays it was built from are copied by the library."""
+
+    def __init__(self, cell, coords, shell_atom, shell_l, shell_nprim, shell_prim0, exps, coefs,
+                 ke_cutoff_ry=None, mesh=None, rel_cutoff_ry=60.0, tau=1e-6,
+                 precision=GPW_FP64, device=0):
+        lib = load()
+        self.handle = None
+        cell = np.asarray(cell, dtype=np.float64)
+        if cell.shape == (3,):
+            cell = np.diag(cell)
+        c = gpw_cell()
+        for i in range(3):
+            for j in range(3):
+                c.a[i][j] = float(cell[i, j])
+        self._keep = [np.ascontiguousarray(coords, dtype=np.float64),
+                      np.ascontiguousarray(shell_atom, dtype=np.int32),
+                      np.ascontiguousarray(shell_l, dtype=np.int32),
+                      np.ascontiguousarray(shell_nprim, dtype=np.int32),
+                      np.ascontiguousarray(shell_prim0, dtype=np.int32),
+                      np.ascontiguousarray(exps, dtype=np.float64),
+                      np.ascontiguousarray(coefs, dtype=np.float64)]
+        k = self._keep
+        b = gpw_basis(natm=k[0].shape[0], coords=k[0].ctypes.data_as(C.POINTER(C.c_double)),
+                      nshell=k[2].shape[0],
+                      shell_atom=k[1].ctypes.data_as(C.POINTER(C.c_int)),
+                      shell_l=k[2].ctypes.data_as(C.POINTER(C.c_int)),
+                      shell_nprim=k[3].ctypes.data_as(C.POINTER(C.c_int)),
+                      shell_prim0=k[4].ctypes.data_as(C.POINTER(C.c_int)),
+                      exps=k[5].ctypes.data_as(C.POINTER(C.c_double)),
+                      coefs=k[6].ctypes.data_as(C.POINTER(C.c_double)))
+        cut = gpw_cutoffs()
+        if mesh is not None:
+            m = np.ascontiguousarray(mesh, dtype=np.int32).reshape(-1, 3)
+            self._keep.append(m)
+            cut.mesh = m.ctypes.data_as(C.POINTER(C.c_int))
+            nl = m.shape[0]
+        else:
+            nl = len(ke_cutoff_ry)
+        if ke_cutoff_ry is not None and len(ke_cutoff_ry):
+            e = np.ascontiguousarray(ke_cutoff_ry, dtype=np.float64)
+            self._keep.append(e)
+            cut.ke_cutoff_ry = e.ctypes.data_as(C.POINTER(C.c_double))
+        cut.nlevels = nl
+        cut.rel_cutoff_ry = float(rel_cutoff_ry)
+        cut.tau = float(tau)
+        cut.precision = int(precision)
+        cut.device = int(device)
+        h = C.c_void_p()
+        _check(lib.gpw_plan(C.byref(c), C.byref(b), C.byref(cut), C.byref(h)))
+        self.handle = h.value
+        self.device = int(device)
+        self.info = self.query()
+
+    def query(self) -> dict:
+        info = gpw_plan_info()
+        _check(load().gpw_plan_query(self.handle, C.byref(info)))
+        nl = info.nlevels
+        return {
+            "nlevels": nl,
+            "mesh": [tuple(info.mesh[l][d] for d in range(3)) for l in range(nl)],
+            "weight": [info.weight[l] for l in range(nl)],
+            "n_grid": [info.n_grid[l] for l in range(nl)],
+            "n_ao": info.n_ao, "natm": info.natm, "precision": info.precision,
+            "n_pairs": [info.n_pairs[l] for l in range(nl)],
+            "n_pairs_class": list(info.n_pairs_class),
+            "n_incidences": [info.n_incidences[l] for l in range(nl)],
+            "n_incidences_class": list(info.n_incidences_class),
+            "sphere_points": info.sphere_points,
+            "flops_rho_block": info.flops_rho_block, "flops_rho_sphere": info.flops_rho_sphere,
+            "flops_mat_block": info.flops_mat_block, "flops_mat_sphere": info.flops_mat_sphere,
+            "flops_grad_block": info.flops_grad_block, "flops_grad_sphere": info.flops_grad_sphere,
+            "device_bytes": info.device_bytes, "max_box_width": info.max_box_width,
+        }
+
+    def close(self):
+        if self.handle is not None:
+            load().gpw_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gpw_plan(*args, **kw) -> PlanHandle:
+    return PlanHandle(*args, **kw)
+
+
+def gpw_plan_destroy(plan: PlanHandle):
+    plan.close()
+
+
+def gpw_plan_query(plan: PlanHandle) -> dict:
+    return plan.query()
+
+
+def gpw_eval_rho(plan: PlanHandle, D, rho, stream=None):
+    arr = _ptr_array([_dev_ptr(r, "rho[l]") for r in rho])
+    _check(load().gpw_eval_rho(plan.handle, _dev_ptr(D, "D"), arr, _stream_handle(stream)))
+
+
+def gpw_eval_mat(plan: PlanHandle, v, M, stream=None):
+    arr = _ptr_array([_dev_ptr(x, "v[l]") for x in v])
+    _check(load().gpw_eval_mat(plan.handle, arr, _dev_ptr(M, "M"), _stream_handle(stream)))
+
+
+def gpw_eval_grad(plan: PlanHandle, D, v, grad, stream=None):
+    arr = _ptr_array([_dev_ptr(x, "v[l]") for x in v])
+    _check(load().gpw_eval_grad(plan.handle, _dev_ptr(D, "D"), arr, _dev_ptr(grad, "grad"),
+                                _stream_handle(stream)))
+
+
+def gpw_eval_batch(tasks, stream=None):
+    """tasks: list of dicts {plan, op, D, v, rho, out} with torch tensors."""
+    n = len(tasks)
+    arr = (gpw_task * max(1, n))()
+    keep = []
+    for i, t in enumerate(tasks):
+        arr[i].plan = t["plan"].handle
+        arr[i].op = int(t["op"])
+        arr[i].D = _dev_ptr(t["D"], "D") if t.get("D") is not None else None
+        if t.get("v") is not None:
+            va = _ptr_array([_dev_ptr(x, "v[l]") for x in t["v"]])
+            keep.append(va)
+            arr[i].v = C.cast(va, C.c_void_p)
+        if t.get("rho") is not None:
+            ra = _ptr_array([_dev_ptr(x, "rho[l]") for x in t["rho"]])
+            keep.append(ra)
+            arr[i].rho = C.cast(ra, C.c_void_p)
+        arr[i].out = _dev_ptr(t["out"], "out") if t.get("out") is not None else None
+    _check(load().gpw_eval_batch(arr, n, _stream_handle(stream)))
+
+
+def gpw_last_error() -> str:
+    return load().gpw_last_error().decode()

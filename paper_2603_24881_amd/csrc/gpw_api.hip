@@ -1,0 +1,318 @@
+// C ABI of libgpw: argument checking, plan construction and the eval entry
+// points.  See include/gpw.h for the contract of every call.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gpw_internal.h"
+
+namespace gpw {
+hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t st, std::string &err);
+hipError_t eval_rho(const gpw_plan_s *pl, const double *D, double *const *rho, hipStream_t st);
+hipError_t eval_mat(const gpw_plan_s *pl, const double *const *v, double *M, hipStream_t st);
+hipError_t eval_grad(const gpw_plan_s *pl, const double *D, const double *const *v, double *grad, hipStream_t st);
+}  // namespace gpw
+
+using namespace gpw;
+
+namespace {
+
+thread_local std::string g_err;
+
+gpw_status fail(gpw_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+gpw_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? GPW_ENOMEM : GPW_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool smooth235(long n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// RAII guard that makes the plan's device current and restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void free_plan(gpw_plan_s *pl)
+{
+    if (!pl) return;
+    for (void *p : pl->allocations) (void)hipFree(p);
+    delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gpw_last_error(void) { return g_err.c_str(); }
+
+gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cutoffs *cut, gpw_plan_t *out)
+{
+    if (!out) return fail(GPW_EINVAL, "gpw_plan: out is NULL");
+    *out = nullptr;
+    if (!cell || !basis || !cut) return fail(GPW_EINVAL, "gpw_plan: NULL cell, basis or cutoffs");
+    // ---- cell
+    double L[3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double a = cell->a[i][j];
+            if (!std::isfinite(a)) return fail(GPW_EINVAL, "gpw_plan: non-finite lattice vector");
+            if (i != j && a != 0.0)
+                return fail(GPW_EUNSUPPORTED, "gpw_plan: only orthorhombic (diagonal) cells are supported");
+        }
+    for (int d = 0; d < 3; ++d) {
+        L[d] = cell->a[d][d];
+        if (!(L[d] > 0.0)) return fail(GPW_EINVAL, "gpw_plan: lattice lengths must be positive");
+    }
+    // ---- basis
+    const gpw_basis &B = *basis;
+    if (B.natm < 1 || B.nshell < 1) return fail(GPW_EINVAL, "gpw_plan: need at least one atom and one shell");
+    if (!B.coords || !B.shell_atom || !B.shell_l || !B.shell_nprim || !B.shell_prim0 || !B.exps || !B.coefs)
+        return fail(GPW_EINVAL, "gpw_plan: NULL basis array");
+    for (int a = 0; a < B.natm; ++a)
+        for (int d = 0; d < 3; ++d) {
+            const double x = B.coords[3 * a + d];
+            if (!std::isfinite(x) || std::fabs(x) > 100.0 * L[d])
+                return fail(GPW_EINVAL, "gpw_plan: atom coordinates must be finite and within 100 cells of the origin");
+        }
+    int n_ao = 0, n_ps = 0;
+    for (int s = 0; s < B.nshell; ++s) {
+        if (B.shell_atom[s] < 0 || B.shell_atom[s] >= B.natm) return fail(GPW_EINVAL, "gpw_plan: shell_atom out of range");
+        if (B.shell_l[s] < 0) return fail(GPW_EINVAL, "gpw_plan: negative angular momentum");
+        if (B.shell_l[s] > 3) return fail(GPW_EUNSUPPORTED, "gpw_plan: angular momentum above 3 (f) is not supported");
+        if (B.shell_nprim[s] < 1 || B.shell_prim0[s] < 0) return fail(GPW_EINVAL, "gpw_plan: bad primitive range");
+        for (int k = 0; k < B.shell_nprim[s]; ++k) {
+            const double e = B.exps[B.shell_prim0[s] + k], c = B.coefs[B.shell_prim0[s] + k];
+            if (!(e > 0.0) || !std::isfinite(e)) return fail(GPW_EINVAL, "gpw_plan: exponents must be positive and finite");
+            if (!std::isfinite(c)) return fail(GPW_EINVAL, "gpw_plan: non-finite coefficient");
+        }
+        n_ao += ncart(B.shell_l[s]);
+        n_ps += B.shell_nprim[s];
+    }
+    // ---- cutoffs
+    const gpw_cutoffs &C = *cut;
+    if (C.nlevels < 1 || C.nlevels > kMaxLevels) return fail(GPW_EINVAL, "gpw_plan: nlevels must be in 1..8");
+    if (!(C.tau > 0.0 && C.tau < 1.0)) return fail(GPW_EINVAL, "gpw_plan: tau must be in (0, 1)");
+    if (C.precision != GPW_FP64 && C.precision != GPW_FP32) return fail(GPW_EINVAL, "gpw_plan: bad precision");
+    if (!C.mesh && !C.ke_cutoff_ry) return fail(GPW_EINVAL, "gpw_plan: need ke_cutoff_ry or mesh");
+    if (C.nlevels > 1 && !C.ke_cutoff_ry) return fail(GPW_EINVAL, "gpw_plan: multigrid needs ke_cutoff_ry");
+    if (C.ke_cutoff_ry) {
+        for (int i = 0; i < C.nlevels; ++i) {
+            if (!(C.ke_cutoff_ry[i] > 0.0) || !std::isfinite(C.ke_cutoff_ry[i]))
+                return fail(GPW_EINVAL, "gpw_plan: cutoffs must be positive");
+            if (i > 0 && !(C.ke_cutoff_ry[i] < C.ke_cutoff_ry[i - 1]))
+                return fail(GPW_EINVAL, "gpw_plan: cutoffs must be strictly descending");
+        }
+        if (C.nlevels > 1 && !(C.rel_cutoff_ry > 0.0)) return fail(GPW_EINVAL, "gpw_plan: rel_cutoff_ry must be positive");
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(GPW_EDEVICE, "gpw_plan: no HIP device");
+    if (C.device < 0 || C.device >= ndev) return fail(GPW_EINVAL, "gpw_plan: device ordinal out of range");
+
+    gpw_plan_s *pl = new (std::nothrow) gpw_plan_s();
+    if (!pl) return fail(GPW_ENOMEM, "gpw_plan: host allocation failed");
+    pl->device = C.device;
+    pl->precision = C.precision;
+    pl->nlevels = C.nlevels;
+    pl->natm = B.natm;
+    pl->nshell = B.nshell;
+    pl->n_ao = n_ao;
+    pl->n_ps = n_ps;
+    pl->tau = C.tau;
+    pl->rel_cut = C.rel_cutoff_ry;
+    for (int d = 0; d < 3; ++d) pl->L[d] = L[d];
+    const double vol = L[0] * L[1] * L[2];
+    for (int l = 0; l < C.nlevels; ++l) {
+        LevelGeom &G = pl->geom[l];
+        pl->cut_ry[l] = C.ke_cutoff_ry ? C.ke_cutoff_ry[l] : 0.0;
+        for (int d = 0; d < 3; ++d) {
+            long n;
+            if (C.mesh) {
+                n = C.mesh[3 * l + d];
+                if (n < 1 || n > (1 << 20)) { free_plan(pl); return fail(GPW_EINVAL, "gpw_plan: mesh out of range"); }
+            } else {
+                n = (long)std::ceil(std::sqrt(C.ke_cutoff_ry[l]) * L[d] / M_PI);
+                if (n < 1) n = 1;
+                while (!smooth235(n)) ++n;
+            }
+            G.N[d] = (int)n;
+            G.nb[d] = (int)((n + 3) / 4);
+            G.h[d] = L[d] / (double)n;
+        }
+        pl->ngrid[l] = (long long)G.N[0] * G.N[1] * G.N[2];
+        pl->nblocks[l] = (long long)G.nb[0] * G.nb[1] * G.nb[2];
+        G.w = vol / (double)pl->ngrid[l];
+    }
+
+    // primitive-shell table (host flattening of the basis arrays)
+    std::vector<int> ps_atom(n_ps), ps_l(n_ps), ps_ao(n_ps);
+    std::vector<double> ps_alpha(n_ps), ps_coef(n_ps);
+    {
+        int q = 0, ao = 0;
+        for (int s = 0; s < B.nshell; ++s) {
+            for (int k = 0; k < B.shell_nprim[s]; ++k, ++q) {
+                ps_atom[q] = B.shell_atom[s];
+                ps_l[q] = B.shell_l[s];
+                ps_ao[q] = ao;
+                ps_alpha[q] = B.exps[B.shell_prim0[s] + k];
+                ps_coef[q] = B.coefs[B.shell_prim0[s] + k];
+            }
+            ao += ncart(B.shell_l[s]);
+        }
+    }
+
+    DeviceGuard guard(pl->device);
+    if (guard.err != hipSuccess) { free_plan(pl); return hip_fail(guard.err, "gpw_plan: hipSetDevice"); }
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) { free_plan(pl); return hip_fail(e, "gpw_plan: hipStreamCreate"); }
+    auto upload = [&](auto *&dst, const auto &vec) -> hipError_t {
+        using V = typename std::remove_reference<decltype(vec)>::type::value_type;
+        hipError_t r = hipMalloc((void **)&dst, sizeof(V) * vec.size());
+        if (r != hipSuccess) return r;
+        pl->allocations.push_back(dst);
+        return hipMemcpy(dst, vec.data(), sizeof(V) * vec.size(), hipMemcpyHostToDevice);
+    };
+    std::vector<double> coords(B.coords, B.coords + 3 * B.natm);
+    if ((e = upload(pl->d_ps_atom, ps_atom)) != hipSuccess || (e = upload(pl->d_ps_l, ps_l)) != hipSuccess ||
+        (e = upload(pl->d_ps_ao, ps_ao)) != hipSuccess || (e = upload(pl->d_ps_alpha, ps_alpha)) != hipSuccess ||
+        (e = upload(pl->d_ps_coef, ps_coef)) != hipSuccess || (e = upload(pl->d_coords, coords)) != hipSuccess) {
+        (void)hipStreamDestroy(st);
+        free_plan(pl);
+        return hip_fail(e, "gpw_plan: upload");
+    }
+    PartitionInput in;
+    in.ps = PsTable{pl->d_ps_atom, pl->d_ps_l, pl->d_ps_ao, pl->d_ps_alpha, pl->d_ps_coef, pl->d_coords, n_ps};
+    for (int d = 0; d < 3; ++d) in.pc.L[d] = L[d];
+    in.pc.logtau = std::log(C.tau);
+    in.pc.rel_cut = C.rel_cutoff_ry;
+    in.pc.nlevels = C.nlevels;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        in.pc.cut[l] = l < C.nlevels ? pl->cut_ry[l] : 0.0;
+        in.pc.geom[l] = pl->geom[l];
+    }
+    std::string err;
+    e = build_partition(pl, in, st, err);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (e != hipSuccess) {
+        free_plan(pl);
+        const gpw_status st_code = e == hipErrorOutOfMemory   ? GPW_ENOMEM
+                                   : e == hipErrorInvalidValue ? GPW_EUNSUPPORTED
+                                                               : GPW_EDEVICE;
+        return fail(st_code, "gpw_plan: " + err);
+    }
+    gpw_plan_info &I = pl->info;
+    I.nlevels = pl->nlevels;
+    for (int l = 0; l < pl->nlevels; ++l) {
+        for (int d = 0; d < 3; ++d) I.mesh[l][d] = pl->geom[l].N[d];
+        I.weight[l] = pl->geom[l].w;
+        I.n_grid[l] = pl->ngrid[l];
+    }
+    I.n_ao = pl->n_ao;
+    I.natm = pl->natm;
+    I.precision = pl->precision;
+    I.device_bytes = (long long)(sizeof(PairRec) * pl->n_pairs + sizeof(int2) * pl->n_inc) +
+                     (long long)sizeof(long long) * (pl->cnt_base[kMaxGroups] + 2) +
+                     (long long)sizeof(int) * pl->blk_off[kMaxGroups] +
+                     (long long)n_ps * (3 * sizeof(int) + 2 * sizeof(double)) + 24LL * pl->natm;
+    *out = pl;
+    return GPW_OK;
+}
+
+gpw_status gpw_plan_destroy(gpw_plan_t plan)
+{
+    if (!plan) return GPW_OK;
+    DeviceGuard guard(plan->device);
+    free_plan(plan);
+    return GPW_OK;
+}
+
+gpw_status gpw_plan_query(gpw_plan_t plan, gpw_plan_info *out)
+{
+    if (!plan || !out) return fail(GPW_EINVAL, "gpw_plan_query: NULL argument");
+    *out = plan->info;
+    return GPW_OK;
+}
+
+static gpw_status check_levels(const gpw_plan_s *pl, const void *const *arr, const char *what)
+{
+    if (!arr) return fail(GPW_EINVAL, std::string(what) + ": NULL level array");
+    for (int l = 0; l < pl->nlevels; ++l)
+        if (!arr[l]) return fail(GPW_EINVAL, std::string(what) + ": NULL level pointer");
+    return GPW_OK;
+}
+
+gpw_status gpw_eval_rho(gpw_plan_t plan, const double *D, double *const *rho, void *stream)
+{
+    if (!plan || !D) return fail(GPW_EINVAL, "gpw_eval_rho: NULL plan or D");
+    gpw_status s = check_levels(plan, (const void *const *)rho, "gpw_eval_rho");
+    if (s != GPW_OK) return s;
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_eval_rho: hipSetDevice");
+    hipError_t e = gpw::eval_rho(plan, D, rho, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_eval_rho");
+}
+
+gpw_status gpw_eval_mat(gpw_plan_t plan, const double *const *v, double *M, void *stream)
+{
+    if (!plan || !M) return fail(GPW_EINVAL, "gpw_eval_mat: NULL plan or M");
+    gpw_status s = check_levels(plan, (const void *const *)v, "gpw_eval_mat");
+    if (s != GPW_OK) return s;
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_eval_mat: hipSetDevice");
+    hipError_t e = gpw::eval_mat(plan, v, M, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_eval_mat");
+}
+
+gpw_status gpw_eval_grad(gpw_plan_t plan, const double *D, const double *const *v, double *grad, void *stream)
+{
+    if (!plan || !D || !grad) return fail(GPW_EINVAL, "gpw_eval_grad: NULL plan, D or grad");
+    gpw_status s = check_levels(plan, (const void *const *)v, "gpw_eval_grad");
+    if (s != GPW_OK) return s;
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_eval_grad: hipSetDevice");
+    hipError_t e = gpw::eval_grad(plan, D, v, grad, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_eval_grad");
+}
+
+gpw_status gpw_eval_batch(const gpw_task *tasks, int ntasks, void *stream)
+{
+    if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(GPW_EINVAL, "gpw_eval_batch: bad task array");
+    for (int i = 0; i < ntasks; ++i) {
+        const gpw_task &t = tasks[i];
+        gpw_status s;
+        switch (t.op) {
+        case GPW_OP_RHO: s = gpw_eval_rho(t.plan, t.D, t.rho, stream); break;
+        case GPW_OP_MAT: s = gpw_eval_mat(t.plan, t.v, t.out, stream); break;
+        case GPW_OP_GRAD: s = gpw_eval_grad(t.plan, t.D, t.v, t.out, stream); break;
+        default: s = fail(GPW_EINVAL, "gpw_eval_batch: unknown op");
+        }
+        if (s != GPW_OK) return s;
+    }
+    return GPW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// Internal declarations shared by the host code and the HIP kernels of libgpw.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "../../include/gpw.h"
+
+namespace gpw {
+
+constexpr int kMaxLevels = GPW_MAX_LEVELS;
+constexpr int kNCls = GPW_NCLASS;
+constexpr int kMaxGroups = kMaxLevels * kNCls;   // (level, class) groups
+
+__host__ __device__ inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+__host__ __device__ constexpr int ncart_c(int l) { return (l + 1) * (l + 2) / 2; }
+// class index of (la, lb), la >= lb: ss ps pp ds dp dd fs fp fd ff
+__host__ __device__ inline int cls_of(int la, int lb) { return la * (la + 1) / 2 + lb; }
+__host__ __device__ inline int cls_la(int c) { return c >= 6 ? 3 : c >= 3 ? 2 : c >= 1 ? 1 : 0; }
+__host__ __device__ inline int cls_lb(int c) { int la = cls_la(c); return c - la * (la + 1) / 2; }
+
+// One canonical pair image (unordered pair of primitive shells plus the
+// lattice translation of the second one).  The first factor carries the
+// higher angular momentum.  192 bytes, read with scalar loads by the
+// grid-block kernels.
+struct alignas(64) PairRec {
+    double A[3];      // centre of the first primitive
+    double AB[3];     // A - B', B' = centre of the second primitive incl. image
+    double P[3];      // product centre
+    double aa, ab;    // exponents of the first and second primitive
+    double Kw;        // w_c * c_a c_b exp(-a b / (a+b) |A - B'|^2), w_c = 1 or 2
+    double R2;        // squared truncation radius
+    double ER;        // exp(-(a+b) R^2): point kept iff envelope >= ER
+    double pad0, pad1;
+    int ao_a, ao_b;   // first AO of each shell
+    int atom_a, atom_b;
+    int lo[3], hi[3]; // unwrapped bounding box of the sphere on the pair's level
+    int la, lb, level, cls;
+    int pad2, pad3;
+};
+static_assert(sizeof(PairRec) == 192, "PairRec layout");
+
+// Per-level geometry passed by value to kernels.
+struct LevelGeom {
+    int N[3];         // mesh
+    int nb[3];        // 4^3 blocks per axis (ceil(N/4))
+    double h[3];      // grid spacing
+    double w;         // quadrature weight Omega / N_l
+};
+
+// Incidence entry: pair index and the fold shifts (unwrapped = wrapped + S*N).
+__host__ __device__ inline int pack_shift(int sx, int sy, int sz)
+{
+    return (sx + 128) | ((sy + 128) << 8) | ((sz + 128) << 16);
+}
+__host__ __device__ inline int shift_of(int packed, int d) { return ((packed >> (8 * d)) & 0xff) - 128; }
+
+// Squared distance from P to the axis-aligned box [x0, x1] per axis.
+__host__ __device__ inline double axis_gap2(double p, double x0, double x1)
+{
+    double g = p < x0 ? x0 - p : (p > x1 ? p - x1 : 0.0);
+    return g * g;
+}
+
+// Conservative factor for block culling: a block is visited when its closest
+// point lies within R (1 + 1e-12); the per-point test decides exactly.
+constexpr double kCullSlack = 1.0 + 1e-12;
+
+// Widest bounding box (points per axis) of one pair image: the pair-major
+// kernels keep its 1-D tables in LDS.
+constexpr int kMaxBoxWidth = 1024;
+
+__device__ inline long long floordiv(long long a, long long b)
+{
+    long long q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+// Per-axis enumeration of the (block, fold shift) pairs whose unwrapped
+// points [4k + S N, min(4k+3, N-1) + S N] meet [lo, hi]: k runs over the
+// wrapped 4-point blocks of a mesh of N points (the last one may be partial),
+// S over the lattice images.  Unwrapped point u = w + S N, wrapped w = 4k + t.
+struct AxisIter {
+    long long S, Send, k, kend;
+    int N, nb, lo, hi;
+    __device__ void start(int lo_, int hi_, int N_, int nb_)
+    {
+        lo = lo_; hi = hi_; N = N_; nb = nb_;
+        S = floordiv(lo, N);
+        Send = floordiv(hi, N);
+        if (hi < lo) { S = Send + 1; return; }
+        set_k();
+        skip_empty();
+    }
+    __device__ void set_k()
+    {
+        long long base = S * N;
+        k = floordiv(lo - base, 4);
+        if (k < 0) k = 0;
+        kend = floordiv(hi - base, 4);
+        if (kend > nb - 1) kend = nb - 1;
+    }
+    __device__ void skip_empty()
+    {
+        while (S <= Send && k > kend) { ++S; if (S <= Send) set_k(); }
+    }
+    __device__ bool valid() const { return S <= Send; }
+    __device__ void next()
+    {
+        if (++k > kend) { ++S; if (S <= Send) { set_k(); skip_empty(); } }
+    }
+    // unwrapped coordinate range of the current block
+    __device__ void range(double h, double &x0, double &x1) const
+    {
+        long long u0 = 4 * k + S * N;
+        long long u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
+        x0 = (double)u0 * h;
+        x1 = (double)u1 * h;
+    }
+};
+
+struct PsTable {
+    const int *atom, *l, *ao;
+    const double *alpha, *coef, *coords;
+    int n;
+};
+
+struct PlanConst {
+    double L[3];
+    double logtau;
+    double rel_cut;
+    int nlevels;
+    double cut[kMaxLevels];
+    LevelGeom geom[kMaxLevels];
+};
+
+struct PartitionInput {
+    PsTable ps;
+    PlanConst pc;
+};
+
+}  // namespace gpw
+
+struct gpw_plan_s {
+    int device = 0;
+    int precision = GPW_FP64;
+    double L[3] = {0, 0, 0};
+    int nlevels = 0;
+    gpw::LevelGeom geom[gpw::kMaxLevels];
+    long long ngrid[gpw::kMaxLevels] = {};
+    long long nblocks[gpw::kMaxLevels] = {};
+    int natm = 0, nshell = 0, n_ao = 0, n_ps = 0;
+    double tau = 1e-6, rel_cut = 60.0;
+    double cut_ry[gpw::kMaxLevels] = {};
+
+    // primitive shells
+    int *d_ps_atom = nullptr, *d_ps_l = nullptr, *d_ps_ao = nullptr;
+    double *d_ps_alpha = nullptr, *d_ps_coef = nullptr, *d_coords = nullptr;
+
+    // canonical pair images grouped by (level, class)
+    gpw::PairRec *d_pairs = nullptr;
+    long long n_pairs = 0;
+    long long group_off[gpw::kMaxGroups + 1] = {};
+
+    // block incidences: counters per (group, block), CSR offsets, entries
+    long long cnt_base[gpw::kMaxGroups + 1] = {};   // counter index base per group
+    long long *d_inc_off = nullptr;                  // cnt_base[last] + 1 offsets
+    int2 *d_inc = nullptr;
+    long long n_inc = 0;
+    // compacted nonempty blocks per group
+    int *d_blk = nullptr;
+    long long blk_off[gpw::kMaxGroups + 1] = {};
+
+    gpw_plan_info info{};
+    std::vector<void *> allocations;
+};
