@@ -69,7 +69,7 @@ def cpu_baseline(system, D_np, V_np, natoms_hint):
     first ``n`` atoms; rho and mat; GFLOP/s with the same per-point flop model
     (ordered pairs, points inside the sphere)."""
     import oracle
-    n = natoms_hint or max(3, int(round(system.natm * 0.02)))
+    n = natoms_hint or max(3, int(round(system.natm * 0.15)))
     mask = np.zeros(system.natm, dtype=np.uint8)
     mask[:n] = 1
     o = oracle.Oracle(system, atom_mask=mask)
@@ -113,6 +113,9 @@ def main():
     info = g.info
     log(f"[bench] plan {plan_s:.2f} s, pairs {sum(info['n_pairs'])}, incidences {sum(info['n_incidences'])}, "
         f"mesh {info['mesh']}, device bytes {info['device_bytes'] / 1e9:.2f} GB")
+    names = ["ss", "ps", "pp", "ds", "dp", "dd", "fs", "fp", "fd", "ff"]
+    log("[bench] per class: " + ", ".join(f"{n}: {p} pairs / {i} blocks" for n, p, i in
+                                          zip(names, info["n_pairs_class"], info["n_incidences_class"])))
     C = synth.draw_orbitals(system)
     Cd = torch.as_tensor(C, device=dev)
     D = (Cd @ Cd.T).contiguous()

@@ -79,13 +79,22 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // --------------------------------------------------------- small kernels
 
+// out = (D + D^T) / 2 through 32x32 LDS tiles (both reads coalesced).
 template <typename T>
-__global__ void k_symmetrize(const double *__restrict__ D, T *__restrict__ out, int n)
+__global__ void __launch_bounds__(256) k_symmetrize(const double *__restrict__ D, T *__restrict__ out, int n)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)n * n) return;
-    const long long r = i / n, c = i % n;
-    out[i] = (T)(0.5 * (D[i] + D[c * n + r]));
+    __shared__ double tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int j = ty; j < 32; j += 8) {
+        const int r = bx + j, c = by + tx;
+        tile[j][tx] = (r < n && c < n) ? D[(long long)r * n + c] : 0.0;
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int r = by + j, c = bx + tx;
+        if (r < n && c < n) out[(long long)r * n + c] = (T)(0.5 * (D[(long long)r * n + c] + tile[tx][j]));
+    }
 }
 
 __global__ void k_fill(double *__restrict__ p, long long n, double v)
@@ -96,78 +105,210 @@ __global__ void k_fill(double *__restrict__ p, long long n, double v)
 
 // ------------------------------------------------------------------ rho
 
-template <int LA, int LB, typename T>
-__global__ void __launch_bounds__(64)
-k_rho(const PairRec *__restrict__ pairs, const int2 *__restrict__ inc,
-      const long long *__restrict__ inc_off, long long cbase, const int *__restrict__ blk,
-      LevelGeom G, const T *__restrict__ Dm, int n_ao, double *__restrict__ rho)
+// Separable Gaussian envelope of a pair image on the 4x4x4 points of a block,
+// exp(-alpha |r - P|^2) = fx[tx] fy[ty] fz[tz], from four exps: the value at
+// the block's first point and one ratio g_d = exp(-2 alpha h_d d_d) per axis;
+// along each axis the factors then follow the grid recursion
+// f_{t+1} = f_t g c^(2t+1), c = exp(-alpha h^2) (Sec. III.A, Eqs. (exp_rr),
+// (exp_rr1)).  Direct exps per point factor when a ratio would overflow.
+__device__ __forceinline__ void block_envelope(double alpha, const double *d, const LevelGeom &G,
+                                               const double *c, double *fx, double *fy, double *fz)
 {
-    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
-    __shared__ T tab_e[64][3][4];
-    __shared__ T tab_d[64][3][4];
-    const int lane = threadIdx.x;
-    const int b = blk[blockIdx.x];
-    const int kz = b % G.nb[2];
-    const int ky = (b / G.nb[2]) % G.nb[1];
-    const int kx = b / (G.nb[2] * G.nb[1]);
-    const int kk[3] = {kx, ky, kz};
-    const long long s0 = inc_off[cbase + b], s1 = inc_off[cbase + b + 1];
-    const int tx = lane >> 4, ty = (lane >> 2) & 3, tz = lane & 3;
-    T acc = T(0);
-    for (long long s = s0; s < s1; s += 64) {
-        const int n = (int)(s1 - s < 64 ? s1 - s : 64);
-        if (lane < n) {
-            const int2 en = inc[s + lane];
-            const PairRec &r = pairs[en.x];
-            const double ap = r.aa + r.ab;
+    double *f[3] = {fx, fy, fz};
+    const double a0 = 2.0 * alpha * G.h[0] * d[0], a1 = 2.0 * alpha * G.h[1] * d[1],
+                 a2 = 2.0 * alpha * G.h[2] * d[2];
+    if (fabs(a0) < 600.0 && fabs(a1) < 600.0 && fabs(a2) < 600.0) {
+        const double an[3] = {a0, a1, a2};
+        f[0][0] = exp(-alpha * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+        f[1][0] = 1.0;
+        f[2][0] = 1.0;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const long long u0 = 4LL * kk[d] + (long long)shift_of(en.y, d) * G.N[d];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const double x = (double)(u0 + t) * G.h[d];
-                    const double dx = x - r.P[d];
-                    tab_e[lane][d][t] = (T)exp(-ap * dx * dx);
-                    tab_d[lane][d][t] = (T)(x - r.A[d]);
-                }
-            }
+        for (int k = 0; k < 3; ++k) {
+            const double c2 = c[k] * c[k];
+            double q = exp(-an[k]) * c[k];
+            f[k][1] = f[k][0] * q;
+            q *= c2;
+            f[k][2] = f[k][1] * q;
+            q *= c2;
+            f[k][3] = f[k][2] * q;
         }
-        __syncthreads();
-        for (int q = 0; q < n; ++q) {
-            const int2 en = inc[s + q];
-            const PairRec &r = pairs[en.x];
-            T E = tab_e[q][0][tx] * tab_e[q][1][ty] * tab_e[q][2][tz];
-            E = (E >= (T)r.ER) ? E : T(0);
-            const T xa = tab_d[q][0][tx], ya = tab_d[q][1][ty], za = tab_d[q][2][tz];
-            T a[NA], bb[NB];
-            monomials<LA, T>(xa, ya, za, a);
-            monomials<LB, T>(xa + (T)r.AB[0], ya + (T)r.AB[1], za + (T)r.AB[2], bb);
-            const T *Dp = Dm + (long long)r.ao_a * n_ao + r.ao_b;
-            T sum = T(0);
+    } else {
 #pragma unroll
-            for (int i = 0; i < NA; ++i) {
-                T t = T(0);
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int j = 0; j < NB; ++j) t += Dp[(long long)i * n_ao + j] * bb[j];
-                sum += a[i] * t;
+            for (int t = 0; t < 4; ++t) {
+                const double x = d[k] + t * G.h[k];
+                f[k][t] = exp(-alpha * x * x);
             }
-            acc += (T)r.Kw * E * sum;
-        }
-        __syncthreads();
-    }
-    const int wx = 4 * kx + tx, wy = 4 * ky + ty, wz = 4 * kz + tz;
-    if (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) {
-        const long long o = ((long long)wx * G.N[1] + wy) * G.N[2] + wz;
-        rho[o] += (double)acc;
     }
 }
 
+// Transpose-reduction through LDS: lane l holds acc[j], its pair images'
+// partial density at point p0 + j (j < NP); afterwards the lane that owns
+// point p0 + j (lane index = point index) holds the sum over all lanes.
+template <int NP, typename T>
+__device__ __forceinline__ void reduce_points(const T *acc, double (*red)[65], int p0, double &out)
+{
+    constexpr int CH = NP < 32 ? NP : 32;   // points per LDS chunk
+    const int lane = threadIdx.x;
+    const int j = lane % CH, part = lane / CH;
+#pragma unroll
+    for (int c0 = 0; c0 < NP; c0 += CH) {
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) red[jj][lane] = (double)acc[c0 + jj];
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll 8
+        for (int m = 0; m < CH; ++m) s += red[j][part * CH + m];
+#pragma unroll
+        for (int o = CH; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+        if (lane == p0 + c0 + j) out = s;
+        __syncthreads();
+    }
+}
+
+// Density of one (level, class) on its nonempty 4x4x4 blocks.  One wave per
+// block; lane = pair image of the block's list (batches of 64), as in Alg. 1,
+// with the image's D sub-block (times K w_c) held in the lane's registers and
+// its contributions accumulated per point in registers over the whole list;
+// one LDS transpose-reduction per block then sums the lanes (instead of a
+// block reduction per point).  NPASS splits the 64 points, NSPLIT the rows of
+// the D sub-block, to bound registers for the high classes.
+template <int LA, int LB, int NPASS, int NSPLIT, int WPE, typename T>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_rho(const PairRec *__restrict__ pairs, const int2 *__restrict__ inc,
+      const long long *__restrict__ inc_off, long long cbase, const int *__restrict__ blk,
+      long long nblk, LevelGeom G, const T *__restrict__ Dm, int n_ao, double *__restrict__ rho)
+{
+    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
+    constexpr int NX = 4 / NPASS;
+    constexpr int NP = 16 * NX;
+    constexpr int NAS = (NA + NSPLIT - 1) / NSPLIT;
+    __shared__ double red[32][65];
+    const int lane = threadIdx.x;
+    const long long item = xcd_item(nblk);
+    if (item >= nblk) return;
+    const int b = blk[item];
+    const int kz = b % G.nb[2];
+    const int ky = (b / G.nb[2]) % G.nb[1];
+    const int kx = b / (G.nb[2] * G.nb[1]);
+    const long long s0 = inc_off[cbase + b], s1 = inc_off[cbase + b + 1];
+    double mine = 0.0;
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+        T acc[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) acc[i] = T(0);
+#pragma unroll
+        for (int sp = 0; sp < NSPLIT; ++sp) {
+            const int i0 = sp * NAS;
+            for (long long s = s0; s < s1; s += 64) {
+                const long long q = s + lane;
+                const bool act = q < s1;
+                const int2 en = inc[act ? q : s0];
+                const PairRec &r = pairs[en.x];
+                const double ap = r.aa + r.ab;
+                const double x0 = (double)(4 * kx + shift_of(en.y, 0) * G.N[0]) * G.h[0];
+                const double y0 = (double)(4 * ky + shift_of(en.y, 1) * G.N[1]) * G.h[1];
+                const double z0 = (double)(4 * kz + shift_of(en.y, 2) * G.N[2]) * G.h[2];
+                double fx[4], fy[4], fz[4];
+                const double dP[3] = {x0 - r.P[0], y0 - r.P[1], z0 - r.P[2]};
+                block_envelope(ap, dP, G, r.c, fx, fy, fz);
+                const T ER = (T)r.ER;
+                const double kw = act ? r.Kw : 0.0;
+                const double xa0 = x0 - r.A[0], ya0 = y0 - r.A[1], za0 = z0 - r.A[2];
+                const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
+                T Dl[NAS * NB];
+                const T *Dp = Dm + (long long)r.ao_a * n_ao + r.ao_b;
+#pragma unroll
+                for (int i = 0; i < NAS; ++i)
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+                        Dl[i * NB + jb] = (i0 + i < NA) ? (T)(kw * (double)Dp[(long long)(i0 + i) * n_ao + jb]) : T(0);
+#pragma unroll
+                for (int ix = 0; ix < NX; ++ix) {
+                    const int tx = pass * NX + ix;
+                    const T xa = (T)(xa0 + tx * G.h[0]);
+                    const T xb = xa + abx;
+                    const T ex = (T)fx[tx];
+#pragma unroll
+                    for (int ty = 0; ty < 4; ++ty) {
+                        const T ya = (T)(ya0 + ty * G.h[1]);
+                        const T yb = ya + aby;
+                        const T exy = ex * (T)fy[ty];
+#pragma unroll
+                        for (int tz = 0; tz < 4; ++tz) {
+                            const T za = (T)(za0 + tz * G.h[2]);
+                            const T zb = za + abz;
+                            T E = exy * (T)fz[tz];
+                            E = (E >= ER) ? E : T(0);
+                            T a[NA], bb[NB];
+                            monomials<LA, T>(xa, ya, za, a);
+                            monomials<LB, T>(xb, yb, zb, bb);
+                            T sum = T(0);
+#pragma unroll
+                            for (int i = 0; i < NAS; ++i) {
+                                if (i0 + i < NA) {
+                                    T t = T(0);
+#pragma unroll
+                                    for (int jb = 0; jb < NB; ++jb) t += Dl[i * NB + jb] * bb[jb];
+                                    sum += a[i0 + i] * t;
+                                }
+                            }
+                            acc[ix * 16 + ty * 4 + tz] += E * sum;
+                        }
+                        // keep the scheduler from interleaving many rows of
+                        // points (it would trade registers for occupancy)
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+        }
+        reduce_points<NP, T>(acc, red, pass * NP, mine);
+    }
+    const int tx = lane >> 4, ty = (lane >> 2) & 3, tz = lane & 3;
+    const int wx = 4 * kx + tx, wy = 4 * ky + ty, wz = 4 * kz + tz;
+    if (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) {
+        const long long o = ((long long)wx * G.N[1] + wy) * G.N[2] + wz;
+        rho[o] += mine;
+    }
+}
+
+// register-budget split of the rho kernel per class: {NPASS, NSPLIT, waves/SIMD}
+template <int LA, int LB> struct RhoSplit { static constexpr int npass = 1, nsplit = 1, wpe = 1; };
+template <> struct RhoSplit<0, 0> { static constexpr int npass = 1, nsplit = 1, wpe = 2; };
+template <> struct RhoSplit<1, 0> { static constexpr int npass = 1, nsplit = 1, wpe = 2; };
+template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, nsplit = 1, wpe = 2; };
+template <> struct RhoSplit<2, 2> { static constexpr int npass = 2, nsplit = 1, wpe = 1; };
+template <> struct RhoSplit<3, 1> { static constexpr int npass = 2, nsplit = 1, wpe = 1; };
+template <> struct RhoSplit<3, 2> { static constexpr int npass = 2, nsplit = 2, wpe = 1; };
+template <> struct RhoSplit<3, 3> { static constexpr int npass = 2, nsplit = 2, wpe = 1; };
+
 // ----------------------------------------------- pair-major traversal (mat, grad)
 
-// 1-D tables of a pair image over u in [lo-3, hi+3] per axis, in LDS:
-// envelope exp(-alpha_p (x_u - P)^2) and offset x_u - A.
+// Per-axis list entry of the blocks a pair image's bounding box meets:
+// wrapped block index k, offset of the block's first point in the 1-D tables,
+// squared distance from P to the block's extent along the axis.
+struct AxisBlock {
+    int k, j0;
+    double gap2;
+};
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// LDS set-up of one pair image: 1-D tables over u in [lo-3, hi+3] per axis
+// (envelope exp(-alpha_p (x_u - P)^2) and offset x_u - A) and the per-axis
+// lists of the blocks (with fold shifts) its bounding box meets.
 template <typename T>
-__device__ __forceinline__ void pair_tables(const PairRec &r, const LevelGeom &G, T *te, T *td, int wmax)
+__device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G, T *te, T *td, int wmax,
+                                           AxisBlock *bl, int emax, int *cnt)
 {
     const double ap = r.aa + r.ab;
     for (int d = 0; d < 3; ++d) {
@@ -179,68 +320,137 @@ __device__ __forceinline__ void pair_tables(const PairRec &r, const LevelGeom &G
             td[d * wmax + i] = (T)(x - r.A[d]);
         }
     }
+    if (threadIdx.x < 3) {
+        const int d = threadIdx.x;
+        AxisIter it;
+        int n = 0;
+        for (it.start(r.lo[d], r.hi[d], G.N[d], G.nb[d]); it.valid() && n < emax; it.next()) {
+            double x0, x1;
+            it.range(G.h[d], x0, x1);
+            AxisBlock e;
+            e.k = (int)it.k;
+            e.j0 = (int)(4 * it.k + it.S * G.N[d]) - (r.lo[d] - 3);
+            e.gap2 = axis_gap2(r.P[d], x0, x1);
+            bl[d * emax + n] = e;
+            ++n;
+        }
+        cnt[d] = n;
+    }
+}
+
+// Copy of a level grid in 4x4x4-block order (block b = (kx nb1 + ky) nb2 + kz,
+// then the 64 points with the z index fastest), zero at the padding points
+// of partial blocks, so that one wave reads a block with one coalesced load.
+__global__ void k_block_grid(const double *__restrict__ v, LevelGeom G, double *__restrict__ vb, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long b = i >> 6;
+    const int t = (int)(i & 63);
+    const int kz = (int)(b % G.nb[2]);
+    const int ky = (int)((b / G.nb[2]) % G.nb[1]);
+    const int kx = (int)(b / ((long long)G.nb[2] * G.nb[1]));
+    const int wx = 4 * kx + (t >> 4), wy = 4 * ky + ((t >> 2) & 3), wz = 4 * kz + (t & 3);
+    vb[i] = (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) ? v[((long long)wx * G.N[1] + wy) * G.N[2] + wz] : 0.0;
 }
 
 // Visit every (block, shift) incidence of the pair image whose block meets
-// the truncation sphere; body(valid, e, xa, ya, za, widx) per lane.
+// the truncation sphere (the incidences the partitioner lists), lane = point
+// of the block.  Along z the blocks that meet the sphere form one run per
+// (x, y) block; it is walked two blocks at a time so that both potential
+// loads are in flight together.  body(f, xa, ya, za): f = v(r) exp(-alpha_p
+// |r-P|^2) inside the sphere, else 0; (xa, ya, za) = r - A.
 template <typename T, typename Body>
-__device__ __forceinline__ void for_each_point(const PairRec &r, const LevelGeom &G, const T *te,
-                                               const T *td, int wmax, Body &&body)
+__device__ __forceinline__ void for_each_point(const PairRec &r, const LevelGeom &G, const T *te, const T *td,
+                                               int wmax, const AxisBlock *bl, int emax, const int *cnt,
+                                               const double *__restrict__ Vb, Body &&body)
 {
     const int lane = threadIdx.x;
     const int tx = lane >> 4, ty = (lane >> 2) & 3, tz = lane & 3;
     const double R2c = r.R2 * kCullSlack;
     const T ER = (T)r.ER;
-    AxisIter ix, iy, iz;
-    for (ix.start(r.lo[0], r.hi[0], G.N[0], G.nb[0]); ix.valid(); ix.next()) {
-        double x0, x1;
-        ix.range(G.h[0], x0, x1);
-        const double gx = axis_gap2(r.P[0], x0, x1);
+    const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]);
+    const AxisBlock *blx = bl, *bly = bl + emax, *blz = bl + 2 * emax;
+    for (int ex = 0; ex < nx; ++ex) {
+        const double gx = uni(blx[ex].gap2);
         if (gx > R2c) continue;
-        const int wx = 4 * (int)ix.k + tx;
-        const int jx = (int)(4 * ix.k + ix.S * G.N[0]) + tx - (r.lo[0] - 3);
-        const T ex = te[jx], xa = td[jx];
-        for (iy.start(r.lo[1], r.hi[1], G.N[1], G.nb[1]); iy.valid(); iy.next()) {
-            double y0, y1;
-            iy.range(G.h[1], y0, y1);
-            const double gy = gx + axis_gap2(r.P[1], y0, y1);
-            if (gy > R2c) continue;
-            const int wy = 4 * (int)iy.k + ty;
-            const int jy = (int)(4 * iy.k + iy.S * G.N[1]) + ty - (r.lo[1] - 3);
-            const T exy = ex * te[wmax + jy], ya = td[wmax + jy];
-            for (iz.start(r.lo[2], r.hi[2], G.N[2], G.nb[2]); iz.valid(); iz.next()) {
-                double z0, z1;
-                iz.range(G.h[2], z0, z1);
-                if (gy + axis_gap2(r.P[2], z0, z1) > R2c) continue;
-                const int wz = 4 * (int)iz.k + tz;
-                const int jz = (int)(4 * iz.k + iz.S * G.N[2]) + tz - (r.lo[2] - 3);
-                T E = exy * te[2 * wmax + jz];
-                const bool valid = (wx < G.N[0]) && (wy < G.N[1]) && (wz < G.N[2]) && (E >= ER);
-                const long long widx = valid ? ((long long)wx * G.N[1] + wy) * G.N[2] + wz : 0;
-                body(valid, E, xa, ya, td[2 * wmax + jz], widx);
+        const int jx = blx[ex].j0 + tx;
+        const int kx = uni(blx[ex].k);
+        const T exv = te[jx], xa = td[jx];
+        for (int ey = 0; ey < ny; ++ey) {
+            const double gxy = gx + uni(bly[ey].gap2);
+            if (gxy > R2c) continue;
+            const int jy = bly[ey].j0 + ty;
+            const int ky = uni(bly[ey].k);
+            const T exy = exv * te[wmax + jy], ya = td[wmax + jy];
+            const long long bxy = ((long long)kx * G.nb[1] + ky) * G.nb[2];
+            const double rem = R2c - gxy;
+            int zlo = 0, zhi = nz - 1;
+            while (zlo < nz && uni(blz[zlo].gap2) > rem) ++zlo;
+            while (zhi >= zlo && uni(blz[zhi].gap2) > rem) --zhi;
+            for (int ez = zlo; ez <= zhi; ez += 2) {
+                const bool two = ez + 1 <= zhi;
+                const int k0 = uni(blz[ez].k), j0 = blz[ez].j0 + tz;
+                const int k1 = uni(blz[two ? ez + 1 : ez].k), j1 = blz[two ? ez + 1 : ez].j0 + tz;
+                const double v0 = Vb[(bxy + k0) * 64 + lane];
+                const double v1 = two ? Vb[(bxy + k1) * 64 + lane] : 0.0;
+                {
+                    const T E = exy * te[2 * wmax + j0];
+                    body((E >= ER) ? (T)v0 * E : T(0), xa, ya, td[2 * wmax + j0]);
+                }
+                if (two) {
+                    const T E = exy * te[2 * wmax + j1];
+                    body((E >= ER) ? (T)v1 * E : T(0), xa, ya, td[2 * wmax + j1]);
+                }
             }
         }
     }
 }
 
+// LDS layout of the pair-major kernels: te[3][wmax], td[3][wmax] (T), then the
+// block lists bl[3][emax] and their counts.
+template <typename T>
+struct PairSmem {
+    static __device__ __forceinline__ void carve(unsigned char *raw, int wmax, int emax, T *&te, T *&td,
+                                                 AxisBlock *&bl, int *&cnt)
+    {
+        te = reinterpret_cast<T *>(raw);
+        td = te + 3 * wmax;
+        size_t off = sizeof(T) * 6 * (size_t)wmax;
+        off = (off + 15) & ~size_t(15);
+        bl = reinterpret_cast<AxisBlock *>(raw + off);
+        cnt = reinterpret_cast<int *>(bl + 3 * emax);
+    }
+    static size_t bytes(int wmax, int emax)
+    {
+        size_t off = sizeof(T) * 6 * (size_t)wmax;
+        off = (off + 15) & ~size_t(15);
+        return off + sizeof(AxisBlock) * 3 * (size_t)emax + 16;
+    }
+};
+
 template <int LA, int LB, typename T>
 __global__ void __launch_bounds__(64)
-k_mat(const PairRec *__restrict__ pairs, long long p0, LevelGeom G, const double *__restrict__ V,
+k_mat(const PairRec *__restrict__ pairs, long long p0, long long np, LevelGeom G, const double *__restrict__ Vb,
       double *__restrict__ M, int n_ao, int wmax)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
-    T *te = reinterpret_cast<T *>(smem_raw);
-    T *td = te + 3 * wmax;
-    const PairRec &r = pairs[p0 + blockIdx.x];
-    pair_tables<T>(r, G, te, td, wmax);
+    T *te, *td;
+    AxisBlock *bl;
+    int *cnt;
+    const int emax = wmax / 4 + 3;
+    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt);
+    const long long item = xcd_item(np);
+    if (item >= np) return;
+    const PairRec &r = pairs[p0 + item];
+    pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
     __syncthreads();
     T acc[NA * NB];
 #pragma unroll
     for (int i = 0; i < NA * NB; ++i) acc[i] = T(0);
     const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
-    for_each_point<T>(r, G, te, td, wmax, [&](bool valid, T E, T xa, T ya, T za, long long widx) {
-        const T f = valid ? (T)V[widx] * E : T(0);
+    for_each_point<T>(r, G, te, td, wmax, bl, emax, cnt, Vb, [&](T f, T xa, T ya, T za) {
         T a[NA], bb[NB];
         monomials<LA, T>(xa, ya, za, a);
         monomials<LB, T>(xa + abx, ya + aby, za + abz, bb);
@@ -266,22 +476,26 @@ k_mat(const PairRec *__restrict__ pairs, long long p0, LevelGeom G, const double
 
 template <int LA, int LB, typename T>
 __global__ void __launch_bounds__(64)
-k_grad(const PairRec *__restrict__ pairs, long long p0, LevelGeom G, const T *__restrict__ Dm, int n_ao,
-       const double *__restrict__ V, double *__restrict__ grad, int wmax)
+k_grad(const PairRec *__restrict__ pairs, long long p0, long long np, LevelGeom G, const T *__restrict__ Dm,
+       int n_ao, const double *__restrict__ Vb, double *__restrict__ grad, int wmax)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
-    T *te = reinterpret_cast<T *>(smem_raw);
-    T *td = te + 3 * wmax;
-    const PairRec &r = pairs[p0 + blockIdx.x];
-    pair_tables<T>(r, G, te, td, wmax);
+    T *te, *td;
+    AxisBlock *bl;
+    int *cnt;
+    const int emax = wmax / 4 + 3;
+    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt);
+    const long long item = xcd_item(np);
+    if (item >= np) return;
+    const PairRec &r = pairs[p0 + item];
+    pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
     __syncthreads();
     T gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
     const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
     const T two_aa = (T)(2.0 * r.aa), two_ab = (T)(2.0 * r.ab);
     const T *Dp = Dm + (long long)r.ao_a * n_ao + r.ao_b;
-    for_each_point<T>(r, G, te, td, wmax, [&](bool valid, T E, T xa, T ya, T za, long long widx) {
-        const T f = valid ? (T)V[widx] * E : T(0);
+    for_each_point<T>(r, G, te, td, wmax, bl, emax, cnt, Vb, [&](T f, T xa, T ya, T za) {
         const T xb = xa + abx, yb = ya + aby, zb = za + abz;
         T a[NA], bb[NB], t[NA], sv[NB];
         monomials<LA, T>(xa, ya, za, a);
@@ -351,7 +565,10 @@ static hipError_t sym_density(const gpw_plan_s *pl, const double *D, T **out, hi
     const long long nn = (long long)pl->n_ao * pl->n_ao;
     hipError_t e = hipMallocAsync((void **)out, sizeof(T) * (size_t)(nn > 0 ? nn : 1), st);
     if (e != hipSuccess) return e;
-    if (nn > 0) hipLaunchKernelGGL(k_symmetrize<T>, dim3(nb256(nn)), dim3(256), 0, st, D, *out, pl->n_ao);
+    if (nn > 0) {
+        const unsigned nt = (unsigned)((pl->n_ao + 31) / 32);
+        hipLaunchKernelGGL(k_symmetrize<T>, dim3(nt, nt), dim3(256), 0, st, D, *out, pl->n_ao);
+    }
     return hipGetLastError();
 }
 
@@ -368,10 +585,13 @@ static hipError_t launch_rho(const gpw_plan_s *pl, const double *D, double *cons
             const long long nb = pl->blk_off[g + 1] - pl->blk_off[g];
             if (nb <= 0) continue;
             dispatch_cls(c, [&](auto la, auto lb) {
-                hipLaunchKernelGGL((k_rho<decltype(la)::value, decltype(lb)::value, T>), dim3((unsigned)nb), dim3(64), 0, st,
+                constexpr int LA_ = decltype(la)::value, LB_ = decltype(lb)::value;
+                hipLaunchKernelGGL((k_rho<LA_, LB_, RhoSplit<LA_, LB_>::npass, RhoSplit<LA_, LB_>::nsplit,
+                                          RhoSplit<LA_, LB_>::wpe, T>),
+                                   dim3(xcd_grid(nb)), dim3(64), 0, st,
                                    (const PairRec *)pl->d_pairs, (const int2 *)pl->d_inc,
                                    (const long long *)pl->d_inc_off, pl->cnt_base[g],
-                                   (const int *)(pl->d_blk + pl->blk_off[g]), pl->geom[l], (const T *)Ds,
+                                   (const int *)(pl->d_blk + pl->blk_off[g]), nb, pl->geom[l], (const T *)Ds,
                                    pl->n_ao, rho[l]);
             });
         }
@@ -382,11 +602,33 @@ static hipError_t launch_rho(const gpw_plan_s *pl, const double *D, double *cons
 }
 
 template <typename T>
-static size_t pair_smem(const gpw_plan_s *pl) { return sizeof(T) * 6 * (size_t)(pl->info.max_box_width + 8); }
+static size_t pair_smem(const gpw_plan_s *pl)
+{
+    const int wmax = pl->info.max_box_width + 8;
+    return PairSmem<T>::bytes(wmax, wmax / 4 + 3);
+}
+
+// Stream-ordered scratch with the block-ordered copies of all level grids.
+static hipError_t block_grids(const gpw_plan_s *pl, const double *const *v, double **vb, long long *off,
+                              hipStream_t st)
+{
+    long long tot = 0;
+    for (int l = 0; l < pl->nlevels; ++l) { off[l] = tot; tot += pl->nblocks[l] * 64; }
+    hipError_t e = hipMallocAsync((void **)vb, sizeof(double) * (size_t)tot, st);
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < pl->nlevels; ++l)
+        hipLaunchKernelGGL(k_block_grid, dim3(nb256(pl->nblocks[l] * 64)), dim3(256), 0, st, v[l], pl->geom[l],
+                           *vb + off[l], pl->nblocks[l] * 64);
+    return hipGetLastError();
+}
 
 template <typename T>
 static hipError_t launch_mat(const gpw_plan_s *pl, const double *const *v, double *M, hipStream_t st)
 {
+    double *vb = nullptr;
+    long long voff[kMaxLevels];
+    hipError_t e0 = block_grids(pl, v, &vb, voff, st);
+    if (e0 != hipSuccess) return e0;
     const long long nn = (long long)pl->n_ao * pl->n_ao;
     hipLaunchKernelGGL(k_fill, dim3(nb256(nn)), dim3(256), 0, st, M, nn, 0.0);
     const int wmax = pl->info.max_box_width + 8;
@@ -396,12 +638,14 @@ static hipError_t launch_mat(const gpw_plan_s *pl, const double *const *v, doubl
             const long long np = pl->group_off[g + 1] - pl->group_off[g];
             if (np <= 0) continue;
             dispatch_cls(c, [&](auto la, auto lb) {
-                hipLaunchKernelGGL((k_mat<decltype(la)::value, decltype(lb)::value, T>), dim3((unsigned)np), dim3(64),
-                                   pair_smem<T>(pl), st, (const PairRec *)pl->d_pairs, pl->group_off[g], pl->geom[l],
-                                   v[l], M, pl->n_ao, wmax);
+                hipLaunchKernelGGL((k_mat<decltype(la)::value, decltype(lb)::value, T>), dim3(xcd_grid(np)), dim3(64),
+                                   pair_smem<T>(pl), st, (const PairRec *)pl->d_pairs, pl->group_off[g], np, pl->geom[l],
+                                   (const double *)(vb + voff[l]), M, pl->n_ao, wmax);
             });
         }
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(vb, st);
+    return e;
 }
 
 template <typename T>
@@ -411,6 +655,10 @@ static hipError_t launch_grad(const gpw_plan_s *pl, const double *D, const doubl
     T *Ds = nullptr;
     hipError_t e = sym_density<T>(pl, D, &Ds, st);
     if (e != hipSuccess) return e;
+    double *vb = nullptr;
+    long long voff[kMaxLevels];
+    e = block_grids(pl, v, &vb, voff, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill, dim3(nb256(3LL * pl->natm)), dim3(256), 0, st, grad, 3LL * pl->natm, 0.0);
     const int wmax = pl->info.max_box_width + 8;
     for (int l = 0; l < pl->nlevels; ++l)
@@ -419,13 +667,14 @@ static hipError_t launch_grad(const gpw_plan_s *pl, const double *D, const doubl
             const long long np = pl->group_off[g + 1] - pl->group_off[g];
             if (np <= 0) continue;
             dispatch_cls(c, [&](auto la, auto lb) {
-                hipLaunchKernelGGL((k_grad<decltype(la)::value, decltype(lb)::value, T>), dim3((unsigned)np), dim3(64),
-                                   pair_smem<T>(pl), st, (const PairRec *)pl->d_pairs, pl->group_off[g], pl->geom[l],
-                                   (const T *)Ds, pl->n_ao, v[l], grad, wmax);
+                hipLaunchKernelGGL((k_grad<decltype(la)::value, decltype(lb)::value, T>), dim3(xcd_grid(np)), dim3(64),
+                                   pair_smem<T>(pl), st, (const PairRec *)pl->d_pairs, pl->group_off[g], np, pl->geom[l],
+                                   (const T *)Ds, pl->n_ao, (const double *)(vb + voff[l]), grad, wmax);
             });
         }
     e = hipGetLastError();
     (void)hipFreeAsync(Ds, st);
+    (void)hipFreeAsync(vb, st);
     return e;
 }
 

@@ -25,8 +25,7 @@ __host__ __device__ inline int cls_lb(int c) { int la = cls_la(c); return c - la
 
 // One canonical pair image (unordered pair of primitive shells plus the
 // lattice translation of the second one).  The first factor carries the
-// higher angular momentum.  192 bytes, read with scalar loads by the
-// grid-block kernels.
+// higher angular momentum.  256 bytes.
 struct alignas(64) PairRec {
     double A[3];      // centre of the first primitive
     double AB[3];     // A - B', B' = centre of the second primitive incl. image
@@ -35,14 +34,15 @@ struct alignas(64) PairRec {
     double Kw;        // w_c * c_a c_b exp(-a b / (a+b) |A - B'|^2), w_c = 1 or 2
     double R2;        // squared truncation radius
     double ER;        // exp(-(a+b) R^2): point kept iff envelope >= ER
-    double pad0, pad1;
+    double c[3];      // exp(-(a+b) h_d^2) on the pair's level (grid-step factor)
+    double pad[6];
     int ao_a, ao_b;   // first AO of each shell
     int atom_a, atom_b;
     int lo[3], hi[3]; // unwrapped bounding box of the sphere on the pair's level
     int la, lb, level, cls;
     int pad2, pad3;
 };
-static_assert(sizeof(PairRec) == 192, "PairRec layout");
+static_assert(sizeof(PairRec) == 256, "PairRec layout");
 
 // Per-level geometry passed by value to kernels.
 struct LevelGeom {
@@ -123,6 +123,17 @@ struct AxisIter {
         x1 = (double)u1 * h;
     }
 };
+
+// Work item of this workgroup such that each of the 8 XCDs (workgroups are
+// dealt to them round robin) walks one contiguous eighth of a list of n items;
+// the grid holds 8 * ceil(n / 8) workgroups and items >= n do nothing.
+__device__ inline long long xcd_item(long long n)
+{
+    const long long per = (n + 7) / 8;
+    const long long b = blockIdx.x;
+    return (b % 8) * per + b / 8;
+}
+inline unsigned xcd_grid(long long n) { return (unsigned)(8 * ((n + 7) / 8)); }
 
 struct PsTable {
     const int *atom, *l, *ao;

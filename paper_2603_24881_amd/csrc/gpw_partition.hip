@@ -118,7 +118,8 @@ k_pairs(PsTable ps, PlanConst pc, unsigned long long *group_cnt, const long long
                 r.Kw = wc * ca * cb * exp(-mu * d2);
                 r.R2 = R * R;
                 r.ER = exp(-ap * R * R);
-                r.pad0 = r.pad1 = 0.0;
+                for (int d = 0; d < 3; ++d) r.c[d] = exp(-ap * G.h[d] * G.h[d]);
+                for (int d = 0; d < 6; ++d) r.pad[d] = 0.0;
                 r.ao_a = ps.ao[fa];
                 r.ao_b = ps.ao[fb];
                 r.atom_a = ps.atom[fa];
@@ -199,6 +200,52 @@ k_incidences(const PairRec *pairs, long long npairs, PlanConst pc, const long lo
         atomicAdd(&stats[2 * g + 0], (double)npts);
         atomicAdd(&stats[2 * g + 1], (double)ninc);
     }
+}
+
+// ------------------------------------------------------- spatial ordering
+
+// Pairs of one (level, class) group are reordered by a coarse spatial cell of
+// their product centre (16 cells per axis, Morton order), so that pair images
+// processed at the same time by one XCD touch nearby grid points and D rows.
+constexpr int kCellBits = 4;
+constexpr int kCells = 1 << (3 * kCellBits);
+
+__device__ inline unsigned morton3(unsigned x, unsigned y, unsigned z)
+{
+    unsigned m = 0;
+    for (int b = 0; b < kCellBits; ++b)
+        m |= (((x >> b) & 1u) << (3 * b + 2)) | (((y >> b) & 1u) << (3 * b + 1)) | (((z >> b) & 1u) << (3 * b));
+    return m;
+}
+
+__global__ void __launch_bounds__(256)
+k_cell_count(const PairRec *pairs, long long n, PlanConst pc, unsigned *hist, unsigned *key_out)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const PairRec &r = pairs[p];
+    unsigned c[3];
+    for (int d = 0; d < 3; ++d) {
+        double f = r.P[d] / pc.L[d];
+        f -= floor(f);
+        int ci = (int)(f * (1 << kCellBits));
+        c[d] = (unsigned)min(max(ci, 0), (1 << kCellBits) - 1);
+    }
+    const unsigned key = (unsigned)(r.level * kNCls + r.cls) * kCells + morton3(c[0], c[1], c[2]);
+    key_out[p] = key;
+    atomicAdd(&hist[key], 1u);
+}
+
+__global__ void __launch_bounds__(256)
+k_cell_scatter(const PairRec *in, long long n, const unsigned *key, const long long *off, unsigned *cur,
+               const unsigned *hist, PairRec *out, int *err_flag)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const unsigned k = key[p];
+    const unsigned pos = atomicAdd(&cur[k], 1u);
+    if (pos >= hist[k]) { atomicOr(err_flag, 1); return; }
+    out[off[k] + pos] = in[p];
 }
 
 // ------------------------------------------------------------------ scans
@@ -360,6 +407,34 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         hipLaunchKernelGGL(k_pairs<true>, dim3(nblk(nn, 256)), dim3(256), 0, st, in.ps, in.pc,
                            (unsigned long long *)nullptr, (const long long *)d_goff, d_gcur, pl->d_pairs, d_err);
         PCHK(hipGetLastError());
+        // reorder every group by spatial cell (counting sort on (group, cell))
+        const long long nkeys = (long long)ngroups * kCells;
+        unsigned *d_hist = nullptr, *d_keys = nullptr, *d_hcur = nullptr;
+        long long *d_hoff = nullptr;
+        PairRec *sorted = nullptr;
+        PCHK(hipMalloc(&d_hist, sizeof(unsigned) * (size_t)nkeys));
+        PCHK(hipMalloc(&d_hcur, sizeof(unsigned) * (size_t)nkeys));
+        PCHK(hipMalloc(&d_hoff, sizeof(long long) * (size_t)(nkeys + 1)));
+        PCHK(hipMalloc(&d_keys, sizeof(unsigned) * (size_t)pl->n_pairs));
+        PCHK(hipMalloc(&sorted, sizeof(PairRec) * (size_t)pl->n_pairs));
+        PCHK(hipMemsetAsync(d_hist, 0, sizeof(unsigned) * (size_t)nkeys, st));
+        PCHK(hipMemsetAsync(d_hcur, 0, sizeof(unsigned) * (size_t)nkeys, st));
+        hipLaunchKernelGGL(k_cell_count, dim3(nblk(pl->n_pairs, 256)), dim3(256), 0, st,
+                           (const PairRec *)pl->d_pairs, pl->n_pairs, in.pc, d_hist, d_keys);
+        PCHK(hipGetLastError());
+        PCHK(exclusive_scan<unsigned>(d_hist, nkeys, d_hoff, st));
+        hipLaunchKernelGGL(k_cell_scatter, dim3(nblk(pl->n_pairs, 256)), dim3(256), 0, st,
+                           (const PairRec *)pl->d_pairs, pl->n_pairs, (const unsigned *)d_keys,
+                           (const long long *)d_hoff, d_hcur, (const unsigned *)d_hist, sorted, d_err);
+        PCHK(hipGetLastError());
+        PCHK(hipStreamSynchronize(st));
+        (void)hipFree(pl->d_pairs);
+        pl->allocations.back() = sorted;
+        pl->d_pairs = sorted;
+        (void)hipFree(d_hist);
+        (void)hipFree(d_hcur);
+        (void)hipFree(d_hoff);
+        (void)hipFree(d_keys);
     }
 
     // counters per (group, block)
