@@ -167,23 +167,66 @@ __device__ __forceinline__ void reduce_points(const T *acc, double (*red)[65], i
     }
 }
 
-// Density of one (level, class) on its nonempty 4x4x4 blocks.  One wave per
-// block; lane = pair image of the block's list (batches of 64), as in Alg. 1,
-// with the image's D sub-block (times K w_c) held in the lane's registers and
-// its contributions accumulated per point in registers over the whole list;
-// one LDS transpose-reduction per block then sums the lanes (instead of a
-// block reduction per point).  NPASS splits the 64 points, NSPLIT the rows of
-// the D sub-block, to bound registers for the high classes.
-template <int LA, int LB, int NPASS, int NSPLIT, int WPE, typename T>
+// Kw-scaled, symmetrised D sub-blocks of every pair image of one (level,
+// class) group, packed per pair image (n_a n_b values each), so that the rho
+// kernel reads a pair image's D and geometry in one round of loads.
+template <typename T, int NA, int NB>
+__global__ void __launch_bounds__(256)
+k_pack_density(const PairRec *__restrict__ pairs, long long p0, long long np, const double *__restrict__ D, int n,
+               T *__restrict__ out)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= np * NA * NB) return;
+    const long long lp = e / (NA * NB);
+    const int ij = (int)(e % (NA * NB));
+    const int i = ij / NB, j = ij % NB;
+    const PairRec &r = pairs[p0 + lp];
+    const long long a = r.ao_a + i, b = r.ao_b + j;
+    out[e] = (T)(r.Kw * 0.5 * (D[a * n + b] + D[b * n + a]));
+}
+
+// Per-lane state of one pair image in the rho kernel.
+template <typename T, int NA, int NB>
+struct RhoLane {
+    double A[3], AB[3], P[3], c[3];
+    double ap, ER;
+    T Dk[NA * NB];
+    __device__ __forceinline__ void load(const RhoRec *__restrict__ rr, const T *__restrict__ Dpk, int lp)
+    {
+        const RhoRec &r = rr[lp];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            A[d] = r.A[d];
+            AB[d] = r.AB[d];
+            P[d] = r.P[d];
+            c[d] = r.c[d];
+        }
+        ap = r.ap;
+        ER = r.ER;
+        const T *src = Dpk + (long long)lp * (NA * NB);
+#pragma unroll
+        for (int k = 0; k < NA * NB; ++k) Dk[k] = src[k];
+    }
+};
+
+// Density of one (level, class) group on its nonempty 4x4x4 blocks.  One wave
+// per block; lane = pair image of the block's list (batches of 64), as in
+// Alg. 1.  Each lane holds its image's geometry and Kw-scaled D sub-block in
+// registers and accumulates its contributions to the block's points over the
+// whole list; one LDS transpose-reduction per block sums the lanes (instead of
+// a block reduction per point).  The loads of the next batch (list entries two
+// batches ahead, geometry and D one batch ahead) are issued before the current
+// batch is computed, so their latency hides behind the arithmetic.  NPASS
+// splits the 64 points to bound the accumulator registers.
+template <int LA, int LB, int NPASS, int WPE, typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-k_rho(const PairRec *__restrict__ pairs, const int2 *__restrict__ inc,
-      const long long *__restrict__ inc_off, long long cbase, const int *__restrict__ blk,
-      long long nblk, LevelGeom G, const T *__restrict__ Dm, int n_ao, double *__restrict__ rho)
+k_rho(const RhoRec *__restrict__ rrec, const int2 *__restrict__ inc, const long long *__restrict__ inc_off,
+      long long cbase, const int *__restrict__ blk, long long nblk, int p0, LevelGeom G,
+      const T *__restrict__ Dpk, double *__restrict__ rho)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     constexpr int NX = 4 / NPASS;
     constexpr int NP = 16 * NX;
-    constexpr int NAS = (NA + NSPLIT - 1) / NSPLIT;
     __shared__ double red[32][65];
     const int lane = threadIdx.x;
     const long long item = xcd_item(nblk);
@@ -192,75 +235,67 @@ k_rho(const PairRec *__restrict__ pairs, const int2 *__restrict__ inc,
     const int kz = b % G.nb[2];
     const int ky = (b / G.nb[2]) % G.nb[1];
     const int kx = b / (G.nb[2] * G.nb[1]);
+    const int kk[3] = {kx, ky, kz};
     const long long s0 = inc_off[cbase + b], s1 = inc_off[cbase + b + 1];
+    const RhoRec *rr = rrec + p0;
     double mine = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int pass = 0; pass < NPASS; ++pass) {
         T acc[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i) acc[i] = T(0);
+        // the list entries of the next batch are loaded one batch ahead
+        int2 en1 = inc[s0 + lane < s1 ? s0 + lane : s1 - 1];
+        for (long long s = s0; s < s1; s += 64) {
+            const bool act = s + lane < s1;
+            const int2 en = en1;
+            {
+                const long long q1 = s + 64 + lane;
+                en1 = inc[q1 < s1 ? q1 : s1 - 1];
+            }
+            RhoLane<T, NA, NB> cur;
+            cur.load(rr, Dpk, en.x - p0);
+            double fx[4], fy[4], fz[4];
+            const double x0 = (double)(4 * kk[0] + shift_of(en.y, 0) * G.N[0]) * G.h[0];
+            const double y0 = (double)(4 * kk[1] + shift_of(en.y, 1) * G.N[1]) * G.h[1];
+            const double z0 = (double)(4 * kk[2] + shift_of(en.y, 2) * G.N[2]) * G.h[2];
+            const double dP[3] = {x0 - cur.P[0], y0 - cur.P[1], z0 - cur.P[2]};
+            block_envelope(cur.ap, dP, G, cur.c, fx, fy, fz);
+            const T ER = (T)cur.ER;
+            const T on = act ? T(1) : T(0);
+            const double xa0 = x0 - cur.A[0], ya0 = y0 - cur.A[1], za0 = z0 - cur.A[2];
+            const T abx = (T)cur.AB[0], aby = (T)cur.AB[1], abz = (T)cur.AB[2];
 #pragma unroll
-        for (int sp = 0; sp < NSPLIT; ++sp) {
-            const int i0 = sp * NAS;
-            for (long long s = s0; s < s1; s += 64) {
-                const long long q = s + lane;
-                const bool act = q < s1;
-                const int2 en = inc[act ? q : s0];
-                const PairRec &r = pairs[en.x];
-                const double ap = r.aa + r.ab;
-                const double x0 = (double)(4 * kx + shift_of(en.y, 0) * G.N[0]) * G.h[0];
-                const double y0 = (double)(4 * ky + shift_of(en.y, 1) * G.N[1]) * G.h[1];
-                const double z0 = (double)(4 * kz + shift_of(en.y, 2) * G.N[2]) * G.h[2];
-                double fx[4], fy[4], fz[4];
-                const double dP[3] = {x0 - r.P[0], y0 - r.P[1], z0 - r.P[2]};
-                block_envelope(ap, dP, G, r.c, fx, fy, fz);
-                const T ER = (T)r.ER;
-                const double kw = act ? r.Kw : 0.0;
-                const double xa0 = x0 - r.A[0], ya0 = y0 - r.A[1], za0 = z0 - r.A[2];
-                const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
-                T Dl[NAS * NB];
-                const T *Dp = Dm + (long long)r.ao_a * n_ao + r.ao_b;
+            for (int ix = 0; ix < NX; ++ix) {
+                const int tx = pass * NX + ix;
+                const T xa = (T)(xa0 + tx * G.h[0]);
+                const T xb = xa + abx;
+                const T ex = (T)fx[tx] * on;
 #pragma unroll
-                for (int i = 0; i < NAS; ++i)
+                for (int ty = 0; ty < 4; ++ty) {
+                    const T ya = (T)(ya0 + ty * G.h[1]);
+                    const T yb = ya + aby;
+                    const T exy = ex * (T)fy[ty];
 #pragma unroll
-                    for (int jb = 0; jb < NB; ++jb)
-                        Dl[i * NB + jb] = (i0 + i < NA) ? (T)(kw * (double)Dp[(long long)(i0 + i) * n_ao + jb]) : T(0);
+                    for (int tz = 0; tz < 4; ++tz) {
+                        const T za = (T)(za0 + tz * G.h[2]);
+                        const T zb = za + abz;
+                        T E = exy * (T)fz[tz];
+                        E = (E >= ER) ? E : T(0);
+                        T a[NA], bb[NB];
+                        monomials<LA, T>(xa, ya, za, a);
+                        monomials<LB, T>(xb, yb, zb, bb);
+                        T sum = T(0);
 #pragma unroll
-                for (int ix = 0; ix < NX; ++ix) {
-                    const int tx = pass * NX + ix;
-                    const T xa = (T)(xa0 + tx * G.h[0]);
-                    const T xb = xa + abx;
-                    const T ex = (T)fx[tx];
+                        for (int i = 0; i < NA; ++i) {
+                            T t = T(0);
 #pragma unroll
-                    for (int ty = 0; ty < 4; ++ty) {
-                        const T ya = (T)(ya0 + ty * G.h[1]);
-                        const T yb = ya + aby;
-                        const T exy = ex * (T)fy[ty];
-#pragma unroll
-                        for (int tz = 0; tz < 4; ++tz) {
-                            const T za = (T)(za0 + tz * G.h[2]);
-                            const T zb = za + abz;
-                            T E = exy * (T)fz[tz];
-                            E = (E >= ER) ? E : T(0);
-                            T a[NA], bb[NB];
-                            monomials<LA, T>(xa, ya, za, a);
-                            monomials<LB, T>(xb, yb, zb, bb);
-                            T sum = T(0);
-#pragma unroll
-                            for (int i = 0; i < NAS; ++i) {
-                                if (i0 + i < NA) {
-                                    T t = T(0);
-#pragma unroll
-                                    for (int jb = 0; jb < NB; ++jb) t += Dl[i * NB + jb] * bb[jb];
-                                    sum += a[i0 + i] * t;
-                                }
-                            }
-                            acc[ix * 16 + ty * 4 + tz] += E * sum;
+                            for (int jb = 0; jb < NB; ++jb) t += cur.Dk[i * NB + jb] * bb[jb];
+                            sum += a[i] * t;
                         }
-                        // keep the scheduler from interleaving many rows of
-                        // points (it would trade registers for occupancy)
-                        __builtin_amdgcn_sched_barrier(0);
+                        acc[ix * 16 + ty * 4 + tz] += E * sum;
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
@@ -274,15 +309,16 @@ k_rho(const PairRec *__restrict__ pairs, const int2 *__restrict__ inc,
     }
 }
 
-// register-budget split of the rho kernel per class: {NPASS, NSPLIT, waves/SIMD}
-template <int LA, int LB> struct RhoSplit { static constexpr int npass = 1, nsplit = 1, wpe = 1; };
-template <> struct RhoSplit<0, 0> { static constexpr int npass = 1, nsplit = 1, wpe = 2; };
-template <> struct RhoSplit<1, 0> { static constexpr int npass = 1, nsplit = 1, wpe = 2; };
-template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, nsplit = 1, wpe = 2; };
-template <> struct RhoSplit<2, 2> { static constexpr int npass = 2, nsplit = 1, wpe = 1; };
-template <> struct RhoSplit<3, 1> { static constexpr int npass = 2, nsplit = 1, wpe = 1; };
-template <> struct RhoSplit<3, 2> { static constexpr int npass = 2, nsplit = 2, wpe = 1; };
-template <> struct RhoSplit<3, 3> { static constexpr int npass = 2, nsplit = 2, wpe = 1; };
+// register-budget split of the rho kernel per class: {NPASS, waves/SIMD}
+template <int LA, int LB> struct RhoSplit { static constexpr int npass = 1, wpe = 2; };
+template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, wpe = 1; };
+template <> struct RhoSplit<2, 0> { static constexpr int npass = 1, wpe = 1; };
+template <> struct RhoSplit<2, 1> { static constexpr int npass = 1, wpe = 1; };
+template <> struct RhoSplit<2, 2> { static constexpr int npass = 2, wpe = 1; };
+template <> struct RhoSplit<3, 0> { static constexpr int npass = 1, wpe = 1; };
+template <> struct RhoSplit<3, 1> { static constexpr int npass = 2, wpe = 1; };
+template <> struct RhoSplit<3, 2> { static constexpr int npass = 2, wpe = 1; };
+template <> struct RhoSplit<3, 3> { static constexpr int npass = 4, wpe = 1; };
 
 // ----------------------------------------------- pair-major traversal (mat, grad)
 
@@ -575,29 +611,46 @@ static hipError_t sym_density(const gpw_plan_s *pl, const double *D, T **out, hi
 template <typename T>
 static hipError_t launch_rho(const gpw_plan_s *pl, const double *D, double *const *rho, hipStream_t st)
 {
-    T *Ds = nullptr;
-    hipError_t e = sym_density<T>(pl, D, &Ds, st);
+    // packed Kw-scaled D sub-blocks of every pair image, grouped like the pairs
+    long long dbase[kMaxGroups + 1];
+    dbase[0] = 0;
+    for (int g = 0; g < kMaxGroups; ++g) {
+        const int c = g % kNCls;
+        dbase[g + 1] = dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) * ncart(cls_la(c)) * ncart(cls_lb(c));
+    }
+    T *Dpk = nullptr;
+    hipError_t e = hipMallocAsync((void **)&Dpk, sizeof(T) * (size_t)(dbase[kMaxGroups] > 0 ? dbase[kMaxGroups] : 1), st);
     if (e != hipSuccess) return e;
-    for (int l = 0; l < pl->nlevels; ++l) {
+    for (int l = 0; l < pl->nlevels; ++l)
         hipLaunchKernelGGL(k_fill, dim3(nb256(pl->ngrid[l])), dim3(256), 0, st, rho[l], pl->ngrid[l], 0.0);
+    for (int l = 0; l < pl->nlevels; ++l)
+        for (int c = 0; c < kNCls; ++c) {
+            const int g = l * kNCls + c;
+            const long long np = pl->group_off[g + 1] - pl->group_off[g];
+            if (np <= 0) continue;
+            dispatch_cls(c, [&](auto la, auto lb) {
+                constexpr int NA_ = ncart_c(decltype(la)::value), NB_ = ncart_c(decltype(lb)::value);
+                hipLaunchKernelGGL((k_pack_density<T, NA_, NB_>), dim3(nb256(np * NA_ * NB_)), dim3(256), 0, st,
+                                   (const PairRec *)pl->d_pairs, pl->group_off[g], np, D, pl->n_ao, Dpk + dbase[g]);
+            });
+        }
+    for (int l = 0; l < pl->nlevels; ++l) {
         for (int c = 0; c < kNCls; ++c) {
             const int g = l * kNCls + c;
             const long long nb = pl->blk_off[g + 1] - pl->blk_off[g];
             if (nb <= 0) continue;
             dispatch_cls(c, [&](auto la, auto lb) {
                 constexpr int LA_ = decltype(la)::value, LB_ = decltype(lb)::value;
-                hipLaunchKernelGGL((k_rho<LA_, LB_, RhoSplit<LA_, LB_>::npass, RhoSplit<LA_, LB_>::nsplit,
-                                          RhoSplit<LA_, LB_>::wpe, T>),
-                                   dim3(xcd_grid(nb)), dim3(64), 0, st,
-                                   (const PairRec *)pl->d_pairs, (const int2 *)pl->d_inc,
-                                   (const long long *)pl->d_inc_off, pl->cnt_base[g],
-                                   (const int *)(pl->d_blk + pl->blk_off[g]), nb, pl->geom[l], (const T *)Ds,
-                                   pl->n_ao, rho[l]);
+                hipLaunchKernelGGL((k_rho<LA_, LB_, RhoSplit<LA_, LB_>::npass, RhoSplit<LA_, LB_>::wpe, T>),
+                                   dim3(xcd_grid(nb)), dim3(64), 0, st, (const RhoRec *)pl->d_rrec,
+                                   (const int2 *)pl->d_inc, (const long long *)pl->d_inc_off, pl->cnt_base[g],
+                                   (const int *)(pl->d_blk + pl->blk_off[g]), nb, (int)pl->group_off[g], pl->geom[l],
+                                   (const T *)(Dpk + dbase[g]), rho[l]);
             });
         }
     }
     e = hipGetLastError();
-    (void)hipFreeAsync(Ds, st);
+    (void)hipFreeAsync(Dpk, st);
     return e;
 }
 

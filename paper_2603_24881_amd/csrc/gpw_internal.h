@@ -44,6 +44,19 @@ struct alignas(64) PairRec {
 };
 static_assert(sizeof(PairRec) == 256, "PairRec layout");
 
+// Compact per-pair geometry read by the rho kernel (one 128-byte line).
+struct alignas(128) RhoRec {
+    double A[3];      // centre of the first primitive
+    double AB[3];     // A - B'
+    double P[3];      // product centre
+    double ap;        // alpha_p
+    double Kw;        // w_c c_a c_b exp(-a b / (a+b) |A - B'|^2)
+    double ER;        // exp(-alpha_p R^2)
+    double c[3];      // exp(-alpha_p h_d^2)
+    double pad;
+};
+static_assert(sizeof(RhoRec) == 128, "RhoRec layout");
+
 // Per-level geometry passed by value to kernels.
 struct LevelGeom {
     int N[3];         // mesh
@@ -175,6 +188,7 @@ struct gpw_plan_s {
 
     // canonical pair images grouped by (level, class)
     gpw::PairRec *d_pairs = nullptr;
+    gpw::RhoRec *d_rrec = nullptr;   // compact copy for the rho kernel
     long long n_pairs = 0;
     long long group_off[gpw::kMaxGroups + 1] = {};
 

@@ -248,6 +248,25 @@ k_cell_scatter(const PairRec *in, long long n, const unsigned *key, const long l
     out[off[k] + pos] = in[p];
 }
 
+__global__ void __launch_bounds__(256) k_rho_records(const PairRec *pairs, long long n, RhoRec *out)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const PairRec &r = pairs[p];
+    RhoRec o;
+    for (int d = 0; d < 3; ++d) {
+        o.A[d] = r.A[d];
+        o.AB[d] = r.AB[d];
+        o.P[d] = r.P[d];
+        o.c[d] = r.c[d];
+    }
+    o.ap = r.aa + r.ab;
+    o.Kw = r.Kw;
+    o.ER = r.ER;
+    o.pad = 0.0;
+    out[p] = o;
+}
+
 // ------------------------------------------------------------------ scans
 
 __device__ inline long long wave_incl_scan(long long v)
@@ -435,6 +454,13 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         (void)hipFree(d_hcur);
         (void)hipFree(d_hoff);
         (void)hipFree(d_keys);
+    }
+    PCHK(hipMalloc(&pl->d_rrec, sizeof(RhoRec) * (size_t)(pl->n_pairs > 0 ? pl->n_pairs : 1)));
+    pl->allocations.push_back(pl->d_rrec);
+    if (pl->n_pairs > 0) {
+        hipLaunchKernelGGL(k_rho_records, dim3(nblk(pl->n_pairs, 256)), dim3(256), 0, st,
+                           (const PairRec *)pl->d_pairs, pl->n_pairs, pl->d_rrec);
+        PCHK(hipGetLastError());
     }
 
     // counters per (group, block)
