@@ -424,19 +424,25 @@ __device__ __forceinline__ void for_each_point(const PairRec &r, const LevelGeom
             int zlo = 0, zhi = nz - 1;
             while (zlo < nz && uni(blz[zlo].gap2) > rem) ++zlo;
             while (zhi >= zlo && uni(blz[zhi].gap2) > rem) --zhi;
-            for (int ez = zlo; ez <= zhi; ez += 2) {
-                const bool two = ez + 1 <= zhi;
-                const int k0 = uni(blz[ez].k), j0 = blz[ez].j0 + tz;
-                const int k1 = uni(blz[two ? ez + 1 : ez].k), j1 = blz[two ? ez + 1 : ez].j0 + tz;
-                const double v0 = Vb[(bxy + k0) * 64 + lane];
-                const double v1 = two ? Vb[(bxy + k1) * 64 + lane] : 0.0;
-                {
-                    const T E = exy * te[2 * wmax + j0];
-                    body((E >= ER) ? (T)v0 * E : T(0), xa, ya, td[2 * wmax + j0]);
+            // the run of z blocks meeting the sphere, four at a time: the four
+            // potential loads are issued together before any is used
+            for (int ez = zlo; ez <= zhi; ez += 4) {
+                int kz[4], jz[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = ez + u <= zhi ? ez + u : zhi;
+                    kz[u] = uni(blz[e].k);
+                    jz[u] = blz[e].j0 + tz;
                 }
-                if (two) {
-                    const T E = exy * te[2 * wmax + j1];
-                    body((E >= ER) ? (T)v1 * E : T(0), xa, ya, td[2 * wmax + j1]);
+                double vv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) vv[u] = Vb[(bxy + kz[u]) * 64 + lane];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (ez + u <= zhi) {
+                        const T E = exy * te[2 * wmax + jz[u]];
+                        body((E >= ER) ? (T)vv[u] * E : T(0), xa, ya, td[2 * wmax + jz[u]]);
+                    }
                 }
             }
         }

@@ -93,29 +93,35 @@ __device__ inline long long floordiv(long long a, long long b)
     if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
     return q;
 }
+__device__ inline int floordiv(int a, int b)
+{
+    int q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
 
 // Per-axis enumeration of the (block, fold shift) pairs whose unwrapped
 // points [4k + S N, min(4k+3, N-1) + S N] meet [lo, hi]: k runs over the
 // wrapped 4-point blocks of a mesh of N points (the last one may be partial),
 // S over the lattice images.  Unwrapped point u = w + S N, wrapped w = 4k + t.
 struct AxisIter {
-    long long S, Send, k, kend;
+    int S, Send, k, kend;
     int N, nb, lo, hi;
     __device__ void start(int lo_, int hi_, int N_, int nb_)
     {
         lo = lo_; hi = hi_; N = N_; nb = nb_;
-        S = floordiv(lo, N);
-        Send = floordiv(hi, N);
+        S = (int)floordiv(lo, N);
+        Send = (int)floordiv(hi, N);
         if (hi < lo) { S = Send + 1; return; }
         set_k();
         skip_empty();
     }
     __device__ void set_k()
     {
-        long long base = S * N;
-        k = floordiv(lo - base, 4);
+        const int base = S * N;
+        k = (int)floordiv(lo - base, 4);
         if (k < 0) k = 0;
-        kend = floordiv(hi - base, 4);
+        kend = (int)floordiv(hi - base, 4);
         if (kend > nb - 1) kend = nb - 1;
     }
     __device__ void skip_empty()
@@ -130,8 +136,8 @@ struct AxisIter {
     // unwrapped coordinate range of the current block
     __device__ void range(double h, double &x0, double &x1) const
     {
-        long long u0 = 4 * k + S * N;
-        long long u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
+        const int u0 = 4 * k + S * N;
+        const int u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
         x0 = (double)u0 * h;
         x1 = (double)u1 * h;
     }
