@@ -8,9 +8,6 @@
 
 namespace gpw {
 hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t st, std::string &err);
-hipError_t eval_rho(const gpw_plan_s *pl, const double *D, double *const *rho, hipStream_t st);
-hipError_t eval_mat(const gpw_plan_s *pl, const double *const *v, double *M, hipStream_t st);
-hipError_t eval_grad(const gpw_plan_s *pl, const double *D, const double *const *v, double *grad, hipStream_t st);
 }  // namespace gpw
 
 using namespace gpw;
@@ -265,54 +262,69 @@ static gpw_status check_levels(const gpw_plan_s *pl, const void *const *arr, con
     return GPW_OK;
 }
 
+// Validated copy of one task.
+static gpw_status check_task(const gpw_task &t, TaskRef &out, const char *what)
+{
+    if (!t.plan) return fail(GPW_EINVAL, std::string(what) + ": NULL plan");
+    gpw_status s = GPW_OK;
+    switch (t.op) {
+    case GPW_OP_RHO:
+        if (!t.D) return fail(GPW_EINVAL, std::string(what) + ": NULL D");
+        s = check_levels(t.plan, (const void *const *)t.rho, what);
+        break;
+    case GPW_OP_MAT:
+        if (!t.out) return fail(GPW_EINVAL, std::string(what) + ": NULL M");
+        s = check_levels(t.plan, (const void *const *)t.v, what);
+        break;
+    case GPW_OP_GRAD:
+        if (!t.D || !t.out) return fail(GPW_EINVAL, std::string(what) + ": NULL D or grad");
+        s = check_levels(t.plan, (const void *const *)t.v, what);
+        break;
+    default: return fail(GPW_EINVAL, std::string(what) + ": unknown op");
+    }
+    if (s != GPW_OK) return s;
+    out = TaskRef{t.plan, t.op, t.D, t.v, t.rho, t.out};
+    return GPW_OK;
+}
+
+static gpw_status run_tasks(const gpw_task *tasks, int n, void *stream, const char *what)
+{
+    std::vector<TaskRef> refs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        gpw_status s = check_task(tasks[i], refs[(size_t)i], what);
+        if (s != GPW_OK) return s;
+        if (tasks[i].plan->device != tasks[0].plan->device)
+            return fail(GPW_EINVAL, std::string(what) + ": plans on different devices");
+    }
+    if (n == 0) return GPW_OK;
+    DeviceGuard guard(tasks[0].plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, what);
+    hipError_t e = gpw::eval_batch(refs.data(), n, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, what);
+}
+
 gpw_status gpw_eval_rho(gpw_plan_t plan, const double *D, double *const *rho, void *stream)
 {
-    if (!plan || !D) return fail(GPW_EINVAL, "gpw_eval_rho: NULL plan or D");
-    gpw_status s = check_levels(plan, (const void *const *)rho, "gpw_eval_rho");
-    if (s != GPW_OK) return s;
-    DeviceGuard guard(plan->device);
-    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_eval_rho: hipSetDevice");
-    hipError_t e = gpw::eval_rho(plan, D, rho, (hipStream_t)stream);
-    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_eval_rho");
+    gpw_task t{plan, GPW_OP_RHO, D, nullptr, rho, nullptr};
+    return run_tasks(&t, 1, stream, "gpw_eval_rho");
 }
 
 gpw_status gpw_eval_mat(gpw_plan_t plan, const double *const *v, double *M, void *stream)
 {
-    if (!plan || !M) return fail(GPW_EINVAL, "gpw_eval_mat: NULL plan or M");
-    gpw_status s = check_levels(plan, (const void *const *)v, "gpw_eval_mat");
-    if (s != GPW_OK) return s;
-    DeviceGuard guard(plan->device);
-    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_eval_mat: hipSetDevice");
-    hipError_t e = gpw::eval_mat(plan, v, M, (hipStream_t)stream);
-    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_eval_mat");
+    gpw_task t{plan, GPW_OP_MAT, nullptr, v, nullptr, M};
+    return run_tasks(&t, 1, stream, "gpw_eval_mat");
 }
 
 gpw_status gpw_eval_grad(gpw_plan_t plan, const double *D, const double *const *v, double *grad, void *stream)
 {
-    if (!plan || !D || !grad) return fail(GPW_EINVAL, "gpw_eval_grad: NULL plan, D or grad");
-    gpw_status s = check_levels(plan, (const void *const *)v, "gpw_eval_grad");
-    if (s != GPW_OK) return s;
-    DeviceGuard guard(plan->device);
-    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_eval_grad: hipSetDevice");
-    hipError_t e = gpw::eval_grad(plan, D, v, grad, (hipStream_t)stream);
-    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_eval_grad");
+    gpw_task t{plan, GPW_OP_GRAD, D, v, nullptr, grad};
+    return run_tasks(&t, 1, stream, "gpw_eval_grad");
 }
 
 gpw_status gpw_eval_batch(const gpw_task *tasks, int ntasks, void *stream)
 {
     if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(GPW_EINVAL, "gpw_eval_batch: bad task array");
-    for (int i = 0; i < ntasks; ++i) {
-        const gpw_task &t = tasks[i];
-        gpw_status s;
-        switch (t.op) {
-        case GPW_OP_RHO: s = gpw_eval_rho(t.plan, t.D, t.rho, stream); break;
-        case GPW_OP_MAT: s = gpw_eval_mat(t.plan, t.v, t.out, stream); break;
-        case GPW_OP_GRAD: s = gpw_eval_grad(t.plan, t.D, t.v, t.out, stream); break;
-        default: s = fail(GPW_EINVAL, "gpw_eval_batch: unknown op");
-        }
-        if (s != GPW_OK) return s;
-    }
-    return GPW_OK;
+    return run_tasks(tasks, ntasks, stream, "gpw_eval_batch");
 }
 
 }  // extern "C"

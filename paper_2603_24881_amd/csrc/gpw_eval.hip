@@ -1,15 +1,14 @@
 // Collocation (rho), integration (mat) and gradient kernels for gfx950.
 //
 // rho  - grid-block major, after Alg. 1 of the paper, mapped to CDNA: one
-//        wave64 owns one 4x4x4 block of one level, lane = grid point, and
-//        keeps the block's density in a register (no cross-lane reduction, one
-//        write per point).  The pair images of the block are taken in batches
-//        of 64: first lane = pair image, each lane evaluating its image's 1-D
-//        Gaussian envelopes and offsets on the 4 points of every axis into LDS
-//        (the separable factorisation of Sec. III.A, Eqs. (gx), (gab)); then
-//        lane = point, walking the batch with the pair record and the D
-//        sub-block held in scalar registers, the polynomial prefactor of
-//        Eq. (gab) evaluated directly per point as in the paper's GPU kernel.
+//        wave64 owns one 4x4x4 block of one level and walks the block's list
+//        of pair images in batches of 64, lane = pair image.  Each lane holds
+//        its image's geometry and Kw-scaled D sub-block in registers,
+//        evaluates the separable envelope of Sec. III.A (Eqs. (gx), (gab),
+//        (exp_rr)) on the block's 64 points and the polynomial prefactor
+//        directly per point, and accumulates the 64 point values in
+//        registers; one LDS transpose-reduction per block sums the lanes and
+//        each point is written once.
 // mat  - pair major: one wave per pair image walks the 4x4x4 blocks its
 //        truncation sphere meets (the same block set as rho), lane = point,
 //        accumulating the n_a x n_b local integrals (Alg. 2's F^local) in
@@ -20,9 +19,69 @@
 // Every kernel is templated on (l_a, l_b) and on the per-point arithmetic
 // type (double, or float for the FP32 variant; exponents, centres and the
 // cross-level/matrix accumulation stay in double).
+//
+// Launches: a kernel launch covers one (operation, class) for any number of
+// (task, level) segments, described by a table passed by value; a work item
+// (grid block or pair image) finds its segment from the table.  A single
+// evaluation is a batch of one task, so batched and single calls run the
+// same kernels in the same order.
 #include "gpw_internal.h"
 
 namespace gpw {
+
+// ------------------------------------------------------- segment tables
+
+constexpr int kMaxSeg = 16;
+
+// Segments of one launch: segment k owns the workgroups [s[k].item0,
+// s[k+1].item0) (the last one up to total).
+template <typename S>
+struct SegTable {
+    S s[kMaxSeg];
+    long long total;
+    int n;
+};
+
+template <typename S>
+__device__ __forceinline__ int seg_of(const SegTable<S> &t, long long item)
+{
+    int k = 0;
+    for (int j = 1; j < t.n; ++j) k = item >= t.s[j].item0 ? j : k;
+    return k;
+}
+
+// element-wise segments, one 256-thread block per item
+struct FillSeg { long long item0; double *p; long long count; };
+struct GridSeg { long long item0; const double *v; double *vb; long long count; LevelGeom G; };
+struct SymSeg { long long item0; const double *D; void *out; int n, nt; };
+struct PackSeg { long long item0; const PairRec *pairs; const double *D; void *out; long long count; int n; };
+// one wave per grid block (rho) or per pair image (mat, grad)
+// Their workgroup ranges are padded to multiples of 8 and mapped to items
+// with xcd_item inside the segment, so that every segment (a level of a
+// task) is spread over all eight XCDs in contiguous chunks, as a launch of
+// its own would be.
+struct RhoSeg {
+    long long item0;
+    long long count;             // nonempty blocks
+    const RhoRec *rr;            // records of the (level, class) group
+    const int2 *inc;             // (pair image, shift) entries
+    const long long *inc_off;    // CSR offsets of the group's blocks
+    const int *blk;              // nonempty blocks of the group
+    const void *Dpk;             // packed D sub-blocks of the group
+    double *rho;                 // level grid
+    int p0;                      // plan index of the group's first pair image
+    LevelGeom G;
+};
+struct PairSeg {
+    long long item0;
+    long long count;             // pair images
+    const PairRec *pairs;        // records of the (level, class) group
+    const void *Dm;              // grad: symmetrised D
+    const double *Vb;            // block-ordered level potential
+    double *out;                 // mat: M; grad: natm x 3
+    int n_ao, wmax;
+    LevelGeom G;
+};
 
 // ------------------------------------------------------- Cartesian helpers
 
@@ -81,10 +140,15 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // out = (D + D^T) / 2 through 32x32 LDS tiles (both reads coalesced).
 template <typename T>
-__global__ void __launch_bounds__(256) k_symmetrize(const double *__restrict__ D, T *__restrict__ out, int n)
+__global__ void __launch_bounds__(256) k_symmetrize(SegTable<SymSeg> tab)
 {
     __shared__ double tile[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const SymSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const double *__restrict__ D = sg.D;
+    T *__restrict__ out = (T *)sg.out;
+    const int n = sg.n;
+    const int it = (int)(blockIdx.x - sg.item0);
+    const int bx = (it / sg.nt) * 32, by = (it % sg.nt) * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int j = ty; j < 32; j += 8) {
         const int r = bx + j, c = by + tx;
@@ -97,10 +161,11 @@ __global__ void __launch_bounds__(256) k_symmetrize(const double *__restrict__ D
     }
 }
 
-__global__ void k_fill(double *__restrict__ p, long long n, double v)
+__global__ void __launch_bounds__(256) k_fill(SegTable<FillSeg> tab)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    const FillSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long i = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
+    if (i < sg.count) sg.p[i] = 0.0;
 }
 
 // ------------------------------------------------------------------ rho
@@ -172,15 +237,18 @@ __device__ __forceinline__ void reduce_points(const T *acc, double (*red)[65], i
 // kernel reads a pair image's D and geometry in one round of loads.
 template <typename T, int NA, int NB>
 __global__ void __launch_bounds__(256)
-k_pack_density(const PairRec *__restrict__ pairs, long long p0, long long np, const double *__restrict__ D, int n,
-               T *__restrict__ out)
+k_pack_density(SegTable<PackSeg> tab)
 {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= np * NA * NB) return;
+    const PackSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long e = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
+    if (e >= sg.count) return;
+    const double *__restrict__ D = sg.D;
+    const int n = sg.n;
+    T *__restrict__ out = (T *)sg.out;
     const long long lp = e / (NA * NB);
     const int ij = (int)(e % (NA * NB));
     const int i = ij / NB, j = ij % NB;
-    const PairRec &r = pairs[p0 + lp];
+    const PairRec &r = sg.pairs[lp];
     const long long a = r.ao_a + i, b = r.ao_b + j;
     out[e] = (T)(r.Kw * 0.5 * (D[a * n + b] + D[b * n + a]));
 }
@@ -220,24 +288,27 @@ struct RhoLane {
 // splits the 64 points to bound the accumulator registers.
 template <int LA, int LB, int NPASS, int WPE, typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-k_rho(const RhoRec *__restrict__ rrec, const int2 *__restrict__ inc, const long long *__restrict__ inc_off,
-      long long cbase, const int *__restrict__ blk, long long nblk, int p0, LevelGeom G,
-      const T *__restrict__ Dpk, double *__restrict__ rho)
+k_rho(SegTable<RhoSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     constexpr int NX = 4 / NPASS;
     constexpr int NP = 16 * NX;
     __shared__ double red[32][65];
     const int lane = threadIdx.x;
-    const long long item = xcd_item(nblk);
-    if (item >= nblk) return;
-    const int b = blk[item];
+    const RhoSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
+    if (item >= sg.count) return;
+    const LevelGeom &G = sg.G;
+    const int2 *__restrict__ inc = sg.inc;
+    const T *__restrict__ Dpk = (const T *)sg.Dpk;
+    const int p0 = sg.p0;
+    const int b = sg.blk[item];
     const int kz = b % G.nb[2];
     const int ky = (b / G.nb[2]) % G.nb[1];
     const int kx = b / (G.nb[2] * G.nb[1]);
     const int kk[3] = {kx, ky, kz};
-    const long long s0 = inc_off[cbase + b], s1 = inc_off[cbase + b + 1];
-    const RhoRec *rr = rrec + p0;
+    const long long s0 = sg.inc_off[b], s1 = sg.inc_off[b + 1];
+    const RhoRec *rr = sg.rr;
     double mine = 0.0;
 #pragma unroll 1
     for (int pass = 0; pass < NPASS; ++pass) {
@@ -305,7 +376,7 @@ k_rho(const RhoRec *__restrict__ rrec, const int2 *__restrict__ inc, const long 
     const int wx = 4 * kx + tx, wy = 4 * ky + ty, wz = 4 * kz + tz;
     if (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) {
         const long long o = ((long long)wx * G.N[1] + wy) * G.N[2] + wz;
-        rho[o] += mine;
+        sg.rho[o] += mine;
     }
 }
 
@@ -377,10 +448,14 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
 // Copy of a level grid in 4x4x4-block order (block b = (kx nb1 + ky) nb2 + kz,
 // then the 64 points with the z index fastest), zero at the padding points
 // of partial blocks, so that one wave reads a block with one coalesced load.
-__global__ void k_block_grid(const double *__restrict__ v, LevelGeom G, double *__restrict__ vb, long long n)
+__global__ void __launch_bounds__(256) k_block_grid(SegTable<GridSeg> tab)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const GridSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long i = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
+    if (i >= sg.count) return;
+    const LevelGeom &G = sg.G;
+    const double *__restrict__ v = sg.v;
+    double *__restrict__ vb = sg.vb;
     const long long b = i >> 6;
     const int t = (int)(i & 63);
     const int kz = (int)(b % G.nb[2]);
@@ -393,7 +468,7 @@ __global__ void k_block_grid(const double *__restrict__ v, LevelGeom G, double *
 // Visit every (block, shift) incidence of the pair image whose block meets
 // the truncation sphere (the incidences the partitioner lists), lane = point
 // of the block.  Along z the blocks that meet the sphere form one run per
-// (x, y) block; it is walked two blocks at a time so that both potential
+// (x, y) block; it is walked four blocks at a time so that their potential
 // loads are in flight together.  body(f, xa, ya, za): f = v(r) exp(-alpha_p
 // |r-P|^2) inside the sphere, else 0; (xa, ya, za) = r - A.
 template <typename T, typename Body>
@@ -473,19 +548,22 @@ struct PairSmem {
 
 template <int LA, int LB, typename T>
 __global__ void __launch_bounds__(64)
-k_mat(const PairRec *__restrict__ pairs, long long p0, long long np, LevelGeom G, const double *__restrict__ Vb,
-      double *__restrict__ M, int n_ao, int wmax)
+k_mat(SegTable<PairSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
     T *te, *td;
     AxisBlock *bl;
     int *cnt;
+    const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
+    if (item >= sg.count) return;
+    const LevelGeom &G = sg.G;
+    const int wmax = sg.wmax, n_ao = sg.n_ao;
+    const double *__restrict__ Vb = sg.Vb;
     const int emax = wmax / 4 + 3;
     PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt);
-    const long long item = xcd_item(np);
-    if (item >= np) return;
-    const PairRec &r = pairs[p0 + item];
+    const PairRec &r = sg.pairs[item];
     pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
     __syncthreads();
     T acc[NA * NB];
@@ -510,33 +588,36 @@ k_mat(const PairRec *__restrict__ pairs, long long p0, long long np, LevelGeom G
         for (int j = 0; j < NB; ++j) {
             const double v = wave_sum((double)acc[i * NB + j]);
             if (threadIdx.x == 0) {
-                atomicAdd(&M[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * v);
-                atomicAdd(&M[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * v);
+                atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * v);
+                atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * v);
             }
         }
 }
 
 template <int LA, int LB, typename T>
 __global__ void __launch_bounds__(64)
-k_grad(const PairRec *__restrict__ pairs, long long p0, long long np, LevelGeom G, const T *__restrict__ Dm,
-       int n_ao, const double *__restrict__ Vb, double *__restrict__ grad, int wmax)
+k_grad(SegTable<PairSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
     T *te, *td;
     AxisBlock *bl;
     int *cnt;
+    const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
+    if (item >= sg.count) return;
+    const LevelGeom &G = sg.G;
+    const int wmax = sg.wmax, n_ao = sg.n_ao;
+    const double *__restrict__ Vb = sg.Vb;
     const int emax = wmax / 4 + 3;
     PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt);
-    const long long item = xcd_item(np);
-    if (item >= np) return;
-    const PairRec &r = pairs[p0 + item];
+    const PairRec &r = sg.pairs[item];
     pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
     __syncthreads();
     T gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
     const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
     const T two_aa = (T)(2.0 * r.aa), two_ab = (T)(2.0 * r.ab);
-    const T *Dp = Dm + (long long)r.ao_a * n_ao + r.ao_b;
+    const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
     for_each_point<T>(r, G, te, td, wmax, bl, emax, cnt, Vb, [&](T f, T xa, T ya, T za) {
         const T xb = xa + abx, yb = ya + aby, zb = za + abz;
         T a[NA], bb[NB], t[NA], sv[NB];
@@ -574,8 +655,8 @@ k_grad(const PairRec *__restrict__ pairs, long long p0, long long np, LevelGeom 
         const double va = wave_sum((double)gA[d]);
         const double vb = wave_sum((double)gB[d]);
         if (threadIdx.x == 0) {
-            atomicAdd(&grad[3 * r.atom_a + d], scale * va);
-            atomicAdd(&grad[3 * r.atom_b + d], scale * vb);
+            atomicAdd(&sg.out[3 * r.atom_a + d], scale * va);
+            atomicAdd(&sg.out[3 * r.atom_b + d], scale * vb);
         }
     }
 }
@@ -599,158 +680,193 @@ static void dispatch_cls(int c, F &&f)
     }
 }
 
-static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
+static inline long long nb256(long long n) { return (n + 255) / 256; }
+
+// Segments of one (operation, class) and the launches that cover them, at
+// most kMaxSeg segments per launch.
+template <typename S>
+struct SegList {
+    std::vector<S> v;
+    std::vector<long long> items;
+    void add(const S &s, long long n)
+    {
+        if (n <= 0) return;
+        v.push_back(s);
+        items.push_back(n);
+    }
+    // launch(table, grid) once per chunk of at most kMaxSeg segments
+    template <typename L>
+    void launch(L &&fn, bool xcd) const
+    {
+        for (size_t i0 = 0; i0 < v.size(); i0 += kMaxSeg) {
+            SegTable<S> t;
+            t.n = (int)std::min<size_t>(kMaxSeg, v.size() - i0);
+            long long tot = 0;
+            for (int k = 0; k < t.n; ++k) {
+                t.s[k] = v[i0 + k];
+                t.s[k].item0 = tot;
+                tot += xcd ? (long long)xcd_grid(items[i0 + k]) : items[i0 + k];
+            }
+            t.total = tot;
+            fn(t, (unsigned)tot);
+        }
+    }
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Scratch of one task inside the batch's stream-ordered allocation.
+struct TaskScratch {
+    size_t dpk = 0, ds = 0, vb = 0;      // byte offsets
+    long long dbase[kMaxGroups + 1];     // packed-D offsets of the groups (elements)
+    long long voff[kMaxLevels];          // block-grid offsets of the levels (doubles)
+};
 
 template <typename T>
-static hipError_t sym_density(const gpw_plan_s *pl, const double *D, T **out, hipStream_t st)
+static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
 {
-    const long long nn = (long long)pl->n_ao * pl->n_ao;
-    hipError_t e = hipMallocAsync((void **)out, sizeof(T) * (size_t)(nn > 0 ? nn : 1), st);
-    if (e != hipSuccess) return e;
-    if (nn > 0) {
-        const unsigned nt = (unsigned)((pl->n_ao + 31) / 32);
-        hipLaunchKernelGGL(k_symmetrize<T>, dim3(nt, nt), dim3(256), 0, st, D, *out, pl->n_ao);
+    std::vector<TaskScratch> ts(n);
+    size_t bytes = 0;
+    int wmax_all = 8;
+    for (int i = 0; i < n; ++i) {
+        const TaskRef &t = tasks[i];
+        const gpw_plan_s *pl = t.pl;
+        TaskScratch &x = ts[i];
+        if (t.op == GPW_OP_RHO) {
+            x.dbase[0] = 0;
+            for (int g = 0; g < kMaxGroups; ++g) {
+                const int c = g % kNCls;
+                x.dbase[g + 1] =
+                    x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) * ncart(cls_la(c)) * ncart(cls_lb(c));
+            }
+            x.dpk = bytes;
+            bytes += align256(sizeof(T) * (size_t)x.dbase[kMaxGroups]);
+        } else {
+            long long tot = 0;
+            for (int l = 0; l < pl->nlevels; ++l) {
+                x.voff[l] = tot;
+                tot += pl->nblocks[l] * 64;
+            }
+            x.vb = bytes;
+            bytes += align256(sizeof(double) * (size_t)tot);
+            wmax_all = std::max(wmax_all, pl->info.max_box_width + 8);
+            if (t.op == GPW_OP_GRAD) {
+                x.ds = bytes;
+                bytes += align256(sizeof(T) * (size_t)pl->n_ao * pl->n_ao);
+            }
+        }
     }
-    return hipGetLastError();
-}
+    unsigned char *scr = nullptr;
+    hipError_t e = hipMallocAsync((void **)&scr, bytes > 0 ? bytes : 256, st);
+    if (e != hipSuccess) return e;
 
-template <typename T>
-static hipError_t launch_rho(const gpw_plan_s *pl, const double *D, double *const *rho, hipStream_t st)
-{
-    // packed Kw-scaled D sub-blocks of every pair image, grouped like the pairs
-    long long dbase[kMaxGroups + 1];
-    dbase[0] = 0;
-    for (int g = 0; g < kMaxGroups; ++g) {
-        const int c = g % kNCls;
-        dbase[g + 1] = dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) * ncart(cls_la(c)) * ncart(cls_lb(c));
+    // outputs to zero, symmetrised D of gradient tasks, block-ordered potentials
+    SegList<FillSeg> fills;
+    SegList<SymSeg> syms;
+    SegList<GridSeg> grids;
+    for (int i = 0; i < n; ++i) {
+        const TaskRef &t = tasks[i];
+        const gpw_plan_s *pl = t.pl;
+        if (t.op == GPW_OP_RHO) {
+            for (int l = 0; l < pl->nlevels; ++l) fills.add({0, t.rho[l], pl->ngrid[l]}, nb256(pl->ngrid[l]));
+            continue;
+        }
+        const long long cnt = t.op == GPW_OP_MAT ? (long long)pl->n_ao * pl->n_ao : 3LL * pl->natm;
+        fills.add({0, t.out, cnt}, nb256(cnt));
+        for (int l = 0; l < pl->nlevels; ++l) {
+            const long long m = pl->nblocks[l] * 64;
+            grids.add({0, t.v[l], (double *)(scr + ts[i].vb) + ts[i].voff[l], m, pl->geom[l]}, nb256(m));
+        }
+        if (t.op == GPW_OP_GRAD && pl->n_ao > 0) {
+            const int nt = (pl->n_ao + 31) / 32;
+            syms.add({0, t.D, scr + ts[i].ds, pl->n_ao, nt}, (long long)nt * nt);
+        }
     }
-    T *Dpk = nullptr;
-    hipError_t e = hipMallocAsync((void **)&Dpk, sizeof(T) * (size_t)(dbase[kMaxGroups] > 0 ? dbase[kMaxGroups] : 1), st);
-    if (e != hipSuccess) return e;
-    for (int l = 0; l < pl->nlevels; ++l)
-        hipLaunchKernelGGL(k_fill, dim3(nb256(pl->ngrid[l])), dim3(256), 0, st, rho[l], pl->ngrid[l], 0.0);
-    for (int l = 0; l < pl->nlevels; ++l)
-        for (int c = 0; c < kNCls; ++c) {
-            const int g = l * kNCls + c;
-            const long long np = pl->group_off[g + 1] - pl->group_off[g];
-            if (np <= 0) continue;
-            dispatch_cls(c, [&](auto la, auto lb) {
-                constexpr int NA_ = ncart_c(decltype(la)::value), NB_ = ncart_c(decltype(lb)::value);
-                hipLaunchKernelGGL((k_pack_density<T, NA_, NB_>), dim3(nb256(np * NA_ * NB_)), dim3(256), 0, st,
-                                   (const PairRec *)pl->d_pairs, pl->group_off[g], np, D, pl->n_ao, Dpk + dbase[g]);
-            });
+    fills.launch([&](const SegTable<FillSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL(k_fill, dim3(g), dim3(256), 0, st, tb);
+    }, false);
+    syms.launch([&](const SegTable<SymSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL(k_symmetrize<T>, dim3(g), dim3(256), 0, st, tb);
+    }, false);
+    grids.launch([&](const SegTable<GridSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL(k_block_grid, dim3(g), dim3(256), 0, st, tb);
+    }, false);
+
+    for (int c = 0; c < kNCls; ++c) {
+        SegList<PackSeg> packs;
+        SegList<RhoSeg> rhos;
+        SegList<PairSeg> mats, grads;
+        for (int i = 0; i < n; ++i) {
+            const TaskRef &t = tasks[i];
+            const gpw_plan_s *pl = t.pl;
+            const int wmax = pl->info.max_box_width + 8;
+            for (int l = 0; l < pl->nlevels; ++l) {
+                const int g = l * kNCls + c;
+                const long long np = pl->group_off[g + 1] - pl->group_off[g];
+                const PairRec *pairs = (const PairRec *)pl->d_pairs + pl->group_off[g];
+                if (t.op == GPW_OP_RHO) {
+                    T *Dpk = (T *)(scr + ts[i].dpk) + ts[i].dbase[g];
+                    const long long ne = np * ncart(cls_la(c)) * ncart(cls_lb(c));
+                    packs.add({0, pairs, t.D, Dpk, ne, pl->n_ao}, nb256(ne));
+                    RhoSeg r;
+                    r.item0 = 0;
+                    r.count = pl->blk_off[g + 1] - pl->blk_off[g];
+                    r.rr = (const RhoRec *)pl->d_rrec + pl->group_off[g];
+                    r.inc = (const int2 *)pl->d_inc;
+                    r.inc_off = (const long long *)pl->d_inc_off + pl->cnt_base[g];
+                    r.blk = (const int *)pl->d_blk + pl->blk_off[g];
+                    r.Dpk = Dpk;
+                    r.rho = t.rho[l];
+                    r.p0 = (int)pl->group_off[g];
+                    r.G = pl->geom[l];
+                    rhos.add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
+                } else {
+                    PairSeg q;
+                    q.item0 = 0;
+                    q.count = np;
+                    q.pairs = pairs;
+                    q.Dm = t.op == GPW_OP_GRAD ? (const void *)(scr + ts[i].ds) : nullptr;
+                    q.Vb = (const double *)(scr + ts[i].vb) + ts[i].voff[l];
+                    q.out = t.out;
+                    q.n_ao = pl->n_ao;
+                    q.wmax = wmax;
+                    q.G = pl->geom[l];
+                    (t.op == GPW_OP_MAT ? mats : grads).add(q, np);
+                }
+            }
         }
-    for (int l = 0; l < pl->nlevels; ++l) {
-        for (int c = 0; c < kNCls; ++c) {
-            const int g = l * kNCls + c;
-            const long long nb = pl->blk_off[g + 1] - pl->blk_off[g];
-            if (nb <= 0) continue;
-            dispatch_cls(c, [&](auto la, auto lb) {
-                constexpr int LA_ = decltype(la)::value, LB_ = decltype(lb)::value;
-                hipLaunchKernelGGL((k_rho<LA_, LB_, RhoSplit<LA_, LB_>::npass, RhoSplit<LA_, LB_>::wpe, T>),
-                                   dim3(xcd_grid(nb)), dim3(64), 0, st, (const RhoRec *)pl->d_rrec,
-                                   (const int2 *)pl->d_inc, (const long long *)pl->d_inc_off, pl->cnt_base[g],
-                                   (const int *)(pl->d_blk + pl->blk_off[g]), nb, (int)pl->group_off[g], pl->geom[l],
-                                   (const T *)(Dpk + dbase[g]), rho[l]);
-            });
-        }
+        const size_t smem = PairSmem<T>::bytes(wmax_all, wmax_all / 4 + 3);
+        dispatch_cls(c, [&](auto la, auto lb) {
+            constexpr int LA = decltype(la)::value, LB = decltype(lb)::value;
+            constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
+            packs.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_pack_density<T, NA, NB>), dim3(g), dim3(256), 0, st, tb);
+            }, false);
+            rhos.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_rho<LA, LB, RhoSplit<LA, LB>::npass, RhoSplit<LA, LB>::wpe, T>), dim3(g),
+                                   dim3(64), 0, st, tb);
+            }, true);
+            mats.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_mat<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
+            }, true);
+            grads.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_grad<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
+            }, true);
+        });
     }
     e = hipGetLastError();
-    (void)hipFreeAsync(Dpk, st);
+    (void)hipFreeAsync(scr, st);
     return e;
 }
 
-template <typename T>
-static size_t pair_smem(const gpw_plan_s *pl)
+hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st)
 {
-    const int wmax = pl->info.max_box_width + 8;
-    return PairSmem<T>::bytes(wmax, wmax / 4 + 3);
-}
-
-// Stream-ordered scratch with the block-ordered copies of all level grids.
-static hipError_t block_grids(const gpw_plan_s *pl, const double *const *v, double **vb, long long *off,
-                              hipStream_t st)
-{
-    long long tot = 0;
-    for (int l = 0; l < pl->nlevels; ++l) { off[l] = tot; tot += pl->nblocks[l] * 64; }
-    hipError_t e = hipMallocAsync((void **)vb, sizeof(double) * (size_t)tot, st);
-    if (e != hipSuccess) return e;
-    for (int l = 0; l < pl->nlevels; ++l)
-        hipLaunchKernelGGL(k_block_grid, dim3(nb256(pl->nblocks[l] * 64)), dim3(256), 0, st, v[l], pl->geom[l],
-                           *vb + off[l], pl->nblocks[l] * 64);
-    return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t launch_mat(const gpw_plan_s *pl, const double *const *v, double *M, hipStream_t st)
-{
-    double *vb = nullptr;
-    long long voff[kMaxLevels];
-    hipError_t e0 = block_grids(pl, v, &vb, voff, st);
-    if (e0 != hipSuccess) return e0;
-    const long long nn = (long long)pl->n_ao * pl->n_ao;
-    hipLaunchKernelGGL(k_fill, dim3(nb256(nn)), dim3(256), 0, st, M, nn, 0.0);
-    const int wmax = pl->info.max_box_width + 8;
-    for (int l = 0; l < pl->nlevels; ++l)
-        for (int c = 0; c < kNCls; ++c) {
-            const int g = l * kNCls + c;
-            const long long np = pl->group_off[g + 1] - pl->group_off[g];
-            if (np <= 0) continue;
-            dispatch_cls(c, [&](auto la, auto lb) {
-                hipLaunchKernelGGL((k_mat<decltype(la)::value, decltype(lb)::value, T>), dim3(xcd_grid(np)), dim3(64),
-                                   pair_smem<T>(pl), st, (const PairRec *)pl->d_pairs, pl->group_off[g], np, pl->geom[l],
-                                   (const double *)(vb + voff[l]), M, pl->n_ao, wmax);
-            });
-        }
-    const hipError_t e = hipGetLastError();
-    (void)hipFreeAsync(vb, st);
+    std::vector<TaskRef> t64, t32;
+    for (int i = 0; i < n; ++i) (tasks[i].pl->precision == GPW_FP32 ? t32 : t64).push_back(tasks[i]);
+    hipError_t e = hipSuccess;
+    if (!t64.empty()) e = batch_t<double>(t64.data(), (int)t64.size(), st);
+    if (e == hipSuccess && !t32.empty()) e = batch_t<float>(t32.data(), (int)t32.size(), st);
     return e;
-}
-
-template <typename T>
-static hipError_t launch_grad(const gpw_plan_s *pl, const double *D, const double *const *v, double *grad,
-                              hipStream_t st)
-{
-    T *Ds = nullptr;
-    hipError_t e = sym_density<T>(pl, D, &Ds, st);
-    if (e != hipSuccess) return e;
-    double *vb = nullptr;
-    long long voff[kMaxLevels];
-    e = block_grids(pl, v, &vb, voff, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill, dim3(nb256(3LL * pl->natm)), dim3(256), 0, st, grad, 3LL * pl->natm, 0.0);
-    const int wmax = pl->info.max_box_width + 8;
-    for (int l = 0; l < pl->nlevels; ++l)
-        for (int c = 0; c < kNCls; ++c) {
-            const int g = l * kNCls + c;
-            const long long np = pl->group_off[g + 1] - pl->group_off[g];
-            if (np <= 0) continue;
-            dispatch_cls(c, [&](auto la, auto lb) {
-                hipLaunchKernelGGL((k_grad<decltype(la)::value, decltype(lb)::value, T>), dim3(xcd_grid(np)), dim3(64),
-                                   pair_smem<T>(pl), st, (const PairRec *)pl->d_pairs, pl->group_off[g], np, pl->geom[l],
-                                   (const T *)Ds, pl->n_ao, (const double *)(vb + voff[l]), grad, wmax);
-            });
-        }
-    e = hipGetLastError();
-    (void)hipFreeAsync(Ds, st);
-    (void)hipFreeAsync(vb, st);
-    return e;
-}
-
-hipError_t eval_rho(const gpw_plan_s *pl, const double *D, double *const *rho, hipStream_t st)
-{
-    return pl->precision == GPW_FP32 ? launch_rho<float>(pl, D, rho, st) : launch_rho<double>(pl, D, rho, st);
-}
-
-hipError_t eval_mat(const gpw_plan_s *pl, const double *const *v, double *M, hipStream_t st)
-{
-    return pl->precision == GPW_FP32 ? launch_mat<float>(pl, v, M, st) : launch_mat<double>(pl, v, M, st);
-}
-
-hipError_t eval_grad(const gpw_plan_s *pl, const double *D, const double *const *v, double *grad, hipStream_t st)
-{
-    return pl->precision == GPW_FP32 ? launch_grad<float>(pl, D, v, grad, st)
-                                     : launch_grad<double>(pl, D, v, grad, st);
 }
 
 }  // namespace gpw

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 #include <string>
@@ -153,6 +154,12 @@ __device__ inline long long xcd_item(long long n)
     return (b % 8) * per + b / 8;
 }
 inline unsigned xcd_grid(long long n) { return (unsigned)(8 * ((n + 7) / 8)); }
+// xcd_item for workgroup b of a range of xcd_grid(n) workgroups
+__device__ inline long long xcd_local(long long b, long long n)
+{
+    const long long per = (n + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
 
 struct PsTable {
     const int *atom, *l, *ao;
@@ -210,3 +217,16 @@ struct gpw_plan_s {
     gpw_plan_info info{};
     std::vector<void *> allocations;
 };
+
+namespace gpw {
+// One evaluation of a batch (the fields of gpw_task after validation).
+struct TaskRef {
+    const gpw_plan_s *pl;
+    int op;                   // gpw_op
+    const double *D;
+    const double *const *v;
+    double *const *rho;
+    double *out;
+};
+hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st);
+}  // namespace gpw

@@ -3,6 +3,8 @@ outputs allocated as torch tensors on the plan's device.  All evaluation goes
 through the C ABI (``_lib``)."""
 from __future__ import annotations
 
+import numpy as np
+
 from . import _lib
 
 
@@ -23,6 +25,9 @@ class GPW:
         self.n_ao = self.info["n_ao"]
         self.natm = self.info["natm"]
         self.device = device
+        self.coords = np.array(system.coords, dtype=np.float64)
+        self.cell = np.array(system.cell, dtype=np.float64)
+        self.cutoffs_ry = list(system.ke_cutoff_ry) if len(system.ke_cutoff_ry) else None
 
     def _dev(self):
         import torch
@@ -50,6 +55,11 @@ class GPW:
             out = torch.empty((self.natm, 3), dtype=torch.float64, device=self._dev())
         _lib.gpw_eval_grad(self.plan, D, [v.contiguous() for v in V], out, stream)
         return out
+
+    def poisson(self):
+        """Multigrid transfer + Poisson solver for this plan's levels, on its device."""
+        from .poisson import MultigridPoisson
+        return MultigridPoisson(self.cell, self.meshes, self.cutoffs_ry, device=self._dev())
 
     def close(self):
         self.plan.close()

@@ -1,0 +1,324 @@
+"""Serving: continuous batching of Fock-build and gradient requests.
+
+A request names a resident system (its plan stays on the device between
+requests) and carries a density matrix D.  A Fock request returns the
+Coulomb matrix J = eval_mat(v_H) and E_J; a gradient request returns
+dE_J/dR = eval_grad(D, v_H) and E_J, where v_H is the Hartree potential of
+rho = eval_rho(D) from the multigrid Poisson step.
+
+The scheduler runs rounds.  In every round one ``gpw_eval_batch`` call
+carries the collocation task of every request admitted since the last round
+and the integration (or gradient) task of every request that finished its
+collocation in the previous round, so requests of different systems and
+sizes share the same launches; after the batch the Poisson step of the new
+requests runs.  A request therefore completes in two rounds.  Requests that
+arrive while a round is on the device are admitted at the start of the next
+round, in arrival order, as long as the number of active requests stays
+below ``max_active`` and their device memory (plus that of their plan, when
+it is not resident) fits the HBM budget; idle plans are evicted least
+recently used first to make room.  A request that can never fit is
+rejected.
+
+``run_sequential`` is the baseline: the same requests, one at a time in
+arrival order, with the plain single calls.
+
+The scheduler talks to an executor (``GPUExecutor`` here; tests use a
+simulated one) through: register, plan_bytes, request_bytes, load, unload,
+begin, round, single, end, now, sleep_until.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import OrderedDict, deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FOCK, GRAD = "fock", "grad"
+
+
+@dataclass(eq=False)
+class Request:
+    rid: int
+    kind: str                 # FOCK or GRAD
+    system: str               # key of a registered system
+    arrival: float            # seconds after the start of the run
+    seed: int = 0             # seed of the request's density matrix
+    admitted: float = math.nan
+    done: float = math.nan
+    stage: int = 0            # 0: collocation pending, 1: integration pending
+    error: str | None = None
+    result: dict | None = None
+    state: dict = field(default_factory=dict)   # executor-owned buffers
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def poisson_trace(n, rate, sizes=(8, 16, 32, 64, 128, 256), geometries=2, grad_fraction=0.5, seed=2000):
+    """n requests with exponential inter-arrival times of mean 1/rate; system
+    size uniform over ``sizes``, geometry uniform over ``geometries``, kind
+    GRAD with probability grad_fraction."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n)
+    t = np.cumsum(gaps) - gaps[0]
+    size = rng.choice(np.asarray(sizes), size=n)
+    geo = rng.integers(0, geometries, size=n)
+    kind = rng.random(n) < grad_fraction
+    return [Request(i, GRAD if kind[i] else FOCK, system_key(int(size[i]), int(geo[i])), float(t[i]),
+                    seed=int(rng.integers(1 << 30))) for i in range(n)]
+
+
+def system_key(n_waters, geometry):
+    return f"w{n_waters}g{geometry}"
+
+
+class Scheduler:
+    def __init__(self, executor, budget_bytes, max_active=16):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.used = 0
+        self.resident = OrderedDict()     # key -> plan bytes, least recently used first
+        self.users = {}                   # key -> active requests on that plan
+        self.rounds = []                  # per round: (n collocation tasks, n integration tasks)
+
+    # ---------------------------------------------------------- memory
+    def _need(self, r):
+        need = self.ex.request_bytes(r.system, r.kind)
+        if r.system not in self.resident:
+            need += self.ex.plan_bytes(r.system)
+        return need
+
+    def _fits_ever(self, r):
+        return self.ex.request_bytes(r.system, r.kind) + self.ex.plan_bytes(r.system) <= self.budget
+
+    def _reserve(self, r):
+        """Reserve memory for r (loading its plan); False if it does not fit now."""
+        need = self._need(r)
+        if self.used + need > self.budget:
+            for key in list(self.resident):
+                if self.used + need <= self.budget:
+                    break
+                if key != r.system and self.users.get(key, 0) == 0:
+                    self.ex.unload(key)
+                    self.used -= self.resident.pop(key)
+        if self.used + need > self.budget:
+            return False
+        if r.system not in self.resident:
+            self.ex.load(r.system)
+            self.resident[r.system] = self.ex.plan_bytes(r.system)
+        self.resident.move_to_end(r.system)
+        self.used += need
+        self.users[r.system] = self.users.get(r.system, 0) + 1
+        return True
+
+    def _release(self, r):
+        self.used -= self.ex.request_bytes(r.system, r.kind)
+        self.users[r.system] -= 1
+
+    def _admit(self, pending, active, now):
+        while pending and pending[0].arrival <= now and len(active) < self.max_active:
+            r = pending[0]
+            if not self._fits_ever(r):
+                pending.popleft()
+                r.error = "request and plan exceed the HBM budget"
+                continue
+            if not self._reserve(r):
+                break                      # arrival order: later requests wait behind it
+            pending.popleft()
+            r.admitted = now
+            r.stage = 0
+            self.ex.begin(r)
+            active.append(r)
+
+    # ---------------------------------------------------------- runs
+    def run(self, requests):
+        """Continuous batching; returns the requests with times and results."""
+        pending = deque(sorted(requests, key=lambda q: (q.arrival, q.rid)))
+        active = []
+        t0 = self.ex.now()
+        while pending or active:
+            self._admit(pending, active, self.ex.now() - t0)
+            if not active:
+                if pending:
+                    self.ex.sleep_until(t0 + pending[0].arrival)
+                continue
+            s0 = [r for r in active if r.stage == 0]
+            s1 = [r for r in active if r.stage == 1]
+            self.ex.round(s0, s1)
+            now = self.ex.now() - t0
+            self.rounds.append((len(s0), len(s1)))
+            for r in s1:
+                r.done = now
+                self.ex.end(r)
+                self._release(r)
+                active.remove(r)
+            for r in s0:
+                r.stage = 1
+        return requests
+
+    def run_sequential(self, requests):
+        """One request at a time in arrival order, plain single calls."""
+        t0 = self.ex.now()
+        for r in sorted(requests, key=lambda q: (q.arrival, q.rid)):
+            if not self._fits_ever(r):
+                r.error = "request and plan exceed the HBM budget"
+                continue
+            if self.ex.now() - t0 < r.arrival:
+                self.ex.sleep_until(t0 + r.arrival)
+            if not self._reserve(r):
+                raise RuntimeError("budget accounting: an idle server cannot admit a fitting request")
+            r.admitted = self.ex.now() - t0
+            self.ex.begin(r)
+            self.ex.single(r)
+            r.done = self.ex.now() - t0
+            self.ex.end(r)
+            self._release(r)
+        return requests
+
+
+def summarize(requests):
+    """p50 / p99 latency (ms), completed requests per second, rejections."""
+    done = [r for r in requests if r.error is None and not math.isnan(r.done)]
+    if not done:
+        return {"completed": 0, "rejected": sum(r.error is not None for r in requests)}
+    lat = np.array([r.latency for r in done])
+    span = max(r.done for r in done) - min(r.arrival for r in done)
+    return {"completed": len(done), "rejected": sum(r.error is not None for r in requests),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "req_per_s": len(done) / span if span > 0 else math.inf}
+
+
+# ---------------------------------------------------------------- GPU side
+
+class GPUExecutor:
+    """Runs requests on one device through the C ABI.  Plans and their
+    Poisson tables are built at ``register`` (their size is then known) and
+    stay resident until the scheduler unloads them."""
+
+    def __init__(self, device=0, precision="fp64", keep_results=False):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        self.device = device
+        self.precision = precision
+        self.keep = keep_results
+        self.systems = {}
+        self.plans = {}         # key -> (GPW, MultigridPoisson)
+        self.sizes = {}         # key -> plan bytes
+        self.req_sizes = {}     # key -> {kind: bytes}
+        self.n_occ = {}
+
+    def register(self, key, system, resident=True):
+        from .gpw import GPW
+        self.systems[key] = system
+        g = GPW(system, precision=self.precision, device=self.device)
+        p = g.poisson()
+        info = g.info
+        fine = int(np.prod(info["mesh"][0]))
+        ngrid = sum(int(np.prod(m)) for m in info["mesh"])
+        poisson_bytes = 16 * fine * 3 + 16 * sum(int(t.numel()) for t in p.src + p.dst)
+        self.sizes[key] = int(info["device_bytes"]) + poisson_bytes
+        n2 = 8 * info["n_ao"] ** 2
+        grids = 8 * ngrid
+        blocks = 8 * 64 * sum(int(np.prod([(m + 3) // 4 for m in mesh])) for mesh in info["mesh"])
+        packed = 8 * 100 * sum(info["n_pairs"])             # packed D sub-blocks, at most (d|d)
+        common = n2 + 2 * grids + 16 * fine * 3 + max(packed, blocks)
+        self.req_sizes[key] = {FOCK: common + n2, GRAD: common + n2 + 24 * info["natm"]}
+        self.n_occ[key] = system.n_occ
+        if resident:
+            self.plans[key] = (g, p)
+        else:
+            g.close()
+        return self.sizes[key]
+
+    def plan_bytes(self, key):
+        return self.sizes[key]
+
+    def request_bytes(self, key, kind):
+        return self.req_sizes[key][kind]
+
+    def load(self, key):
+        if key not in self.plans:
+            from .gpw import GPW
+            g = GPW(self.systems[key], precision=self.precision, device=self.device)
+            self.plans[key] = (g, g.poisson())
+
+    def unload(self, key):
+        g, _ = self.plans.pop(key)
+        self.torch.cuda.synchronize(self.dev)
+        g.close()
+
+    def density(self, key, seed):
+        """D = C C^T, C an n_ao x n_occ N(0,1) matrix drawn on the device."""
+        torch = self.torch
+        g, _ = self.plans[key]
+        gen = torch.Generator(device=self.dev)
+        gen.manual_seed(seed)
+        C = torch.randn((g.n_ao, self.n_occ[key]), dtype=torch.float64, device=self.dev, generator=gen)
+        return (C @ C.T).contiguous()
+
+    def begin(self, r):
+        g, _ = self.plans[r.system]
+        r.state = {"D": self.density(r.system, r.seed), "rho": g.new_grids()}
+
+    def _finish_poisson(self, r):
+        _, p = self.plans[r.system]
+        v, e = p.solve(r.state["rho"])
+        r.state["v"] = v
+        r.state["E_J"] = e
+        del r.state["rho"]
+
+    def _output(self, r):
+        torch = self.torch
+        g, _ = self.plans[r.system]
+        shape = (g.n_ao, g.n_ao) if r.kind == FOCK else (g.natm, 3)
+        r.state["out"] = torch.empty(shape, dtype=torch.float64, device=self.dev)
+        return r.state["out"]
+
+    def round(self, s0, s1):
+        from . import _lib
+        tasks = []
+        for r in s1:
+            g, _ = self.plans[r.system]
+            out = self._output(r)
+            if r.kind == FOCK:
+                tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_MAT, v=r.state["v"], out=out))
+            else:
+                tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_GRAD, D=r.state["D"], v=r.state["v"], out=out))
+        for r in s0:
+            g, _ = self.plans[r.system]
+            tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_RHO, D=r.state["D"], rho=r.state["rho"]))
+        _lib.gpw_eval_batch(tasks)
+        for r in s0:
+            self._finish_poisson(r)
+        self.torch.cuda.synchronize(self.dev)
+
+    def single(self, r):
+        g, _ = self.plans[r.system]
+        g.rho(r.state["D"], out=r.state["rho"])
+        self._finish_poisson(r)
+        out = self._output(r)
+        if r.kind == FOCK:
+            g.mat(r.state["v"], out=out)
+        else:
+            g.grad(r.state["D"], r.state["v"], out=out)
+        self.torch.cuda.synchronize(self.dev)
+
+    def end(self, r):
+        key = "J" if r.kind == FOCK else "grad"
+        r.result = {"E_J": r.state["E_J"]}
+        if self.keep:
+            r.result[key] = r.state["out"]
+        r.state = {}
+
+    def now(self):
+        return time.perf_counter()
+
+    def sleep_until(self, t):
+        dt = t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)

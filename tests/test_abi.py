@@ -79,3 +79,7 @@ def test_null_arguments():
     assert lib.gpw_eval_mat(None, None, None, None) == 1
     assert lib.gpw_eval_grad(None, None, None, None, None) == 1
     assert lib.gpw_eval_batch(None, -1, None) == 1
+    assert lib.gpw_eval_batch(None, 0, None) == 0
+    one = (_lib.gpw_task * 1)()
+    assert lib.gpw_eval_batch(one, 1, None) == 1          # NULL plan
+    assert "NULL plan" in _lib.gpw_last_error()
