@@ -49,6 +49,7 @@ class _OSys(C.Structure):
         ("rel_cut", C.c_double),
         ("tau", C.c_double),
         ("atom_mask", C.POINTER(C.c_ubyte)),
+        ("mask_either", C.c_int),
     ]
 
 
@@ -84,9 +85,11 @@ def num_threads() -> int:
 class Oracle:
     """Oracle bound to one system.  ``system`` is a ``synth.System``; ``tau``
     overrides its screening threshold; ``atom_mask`` restricts the sum to pairs
-    whose first primitive sits on a selected atom (used for bounded samples)."""
+    whose first primitive sits on a selected atom (used for bounded samples), or
+    with ``mask_either`` to pairs with either primitive on a selected atom (then
+    the gradient rows of the selected atoms are complete)."""
 
-    def __init__(self, system, tau: float | None = None, atom_mask=None):
+    def __init__(self, system, tau: float | None = None, atom_mask=None, mask_either: bool = False):
         self.s = system
         lib = _load()
         self.cell = np.ascontiguousarray(system.cell, dtype=np.float64)
@@ -129,6 +132,7 @@ class Oracle:
         st.tau = self.tau
         st.atom_mask = (self.atom_mask.ctypes.data_as(C.POINTER(C.c_ubyte))
                         if self.atom_mask is not None else None)
+        st.mask_either = 1 if mask_either else 0
         self._st = st
         self.counts = np.zeros(16, dtype=np.int64)
 

@@ -70,6 +70,7 @@ typedef struct {
     double rel_cut;
     double tau;
     const unsigned char *atom_mask;  /* optional: only pairs whose first atom is set */
+    int mask_either;                 /* with atom_mask: pairs with either atom set */
 } osys;
 
 /* ---------------------------------------------------------------- basics */
@@ -180,7 +181,7 @@ static void for_each_pair(const osys *s, pair_fn fn, void *ctx)
         int i = (int)(idx / nps), j = (int)(idx % nps);
         int sa = ps_shell[i], ka = ps_prim[i], sb = ps_shell[j], kb = ps_prim[j];
         int atom_a = s->shell_atom[sa], atom_b = s->shell_atom[sb];
-        if (s->atom_mask && !s->atom_mask[atom_a]) continue;
+        if (s->atom_mask && !s->atom_mask[atom_a] && !(s->mask_either && s->atom_mask[atom_b])) continue;
         opair p;
         p.sa = sa; p.ka = ka; p.sb = sb; p.kb = kb;
         p.la = s->shell_l[sa]; p.lb = s->shell_l[sb];

@@ -25,6 +25,7 @@ class GPWCollocate(torch.autograd.Function):
             raise ValueError("coords differ from the plan's geometry; build a plan for them")
         rho = gpw.rho(D.detach().contiguous())
         ctx.gpw = gpw
+        ctx.coords_device = coords.device
         ctx.save_for_backward(D)
         return tuple(rho)
 
@@ -38,7 +39,9 @@ class GPWCollocate(torch.autograd.Function):
                 g = torch.zeros(tuple(gpw.meshes[l]), dtype=torch.float64, device=D.device)
             V.append((g / gpw.weights[l]).contiguous())
         dD = gpw.mat(V) if ctx.needs_input_grad[0] else None
-        dR = gpw.grad(D.detach().contiguous(), V) if ctx.needs_input_grad[1] else None
+        dR = None
+        if ctx.needs_input_grad[1]:
+            dR = gpw.grad(D.detach().contiguous(), V).to(ctx.coords_device)
         return dD, dR, None
 
 

@@ -465,71 +465,126 @@ __global__ void __launch_bounds__(256) k_block_grid(SegTable<GridSeg> tab)
     vb[i] = (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) ? v[((long long)wx * G.N[1] + wy) * G.N[2] + wz] : 0.0;
 }
 
+// One (x, y) row of blocks of a pair image whose z run meets the sphere:
+// the block-grid offset of its (x, y) block column, the LDS table offsets of
+// its x and y blocks, and the run [zlo, zhi] in the z block list.
+struct BlockRow {
+    int bxy, jx0, jy0, zz;   // zz = zlo | zhi << 16
+};
+
+// Rows of the pair image's blocks, in (x block, y block) order: built by the
+// wave with one candidate row per lane and a ballot compaction.
+__device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, const AxisBlock *bl, int emax,
+                                          const int *cnt, BlockRow *rows)
+{
+    const int lane = threadIdx.x;
+    const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]);
+    const AxisBlock *blx = bl, *bly = bl + emax, *blz = bl + 2 * emax;
+    int nrows = 0;
+    for (int base = 0; base < nx * ny; base += 64) {
+        const int i = base + lane;
+        bool ok = false;
+        BlockRow row;
+        if (i < nx * ny) {
+            const int ex = i / ny, ey = i - ex * ny;
+            const double g = blx[ex].gap2 + bly[ey].gap2;
+            if (g <= R2c) {
+                const double rem = R2c - g;
+                int zlo = 0, zhi = nz - 1;
+                while (zlo < nz && blz[zlo].gap2 > rem) ++zlo;
+                while (zhi >= zlo && blz[zhi].gap2 > rem) --zhi;
+                ok = zlo <= zhi;
+                row.bxy = (blx[ex].k * G.nb[1] + bly[ey].k) * G.nb[2];
+                row.jx0 = blx[ex].j0;
+                row.jy0 = bly[ey].j0;
+                row.zz = zlo | (zhi << 16);
+            }
+        }
+        const unsigned long long m = __ballot(ok);
+        if (ok) rows[nrows + __popcll(m & ((1ull << lane) - 1))] = row;
+        nrows += __popcll(m);
+    }
+    return nrows;
+}
+
 // Visit every (block, shift) incidence of the pair image whose block meets
 // the truncation sphere (the incidences the partitioner lists), lane = point
-// of the block.  Along z the blocks that meet the sphere form one run per
-// (x, y) block; it is walked four blocks at a time so that their potential
-// loads are in flight together.  body(f, xa, ya, za): f = v(r) exp(-alpha_p
-// |r-P|^2) inside the sphere, else 0; (xa, ya, za) = r - A.
+// of the block, row by row in (x, y, z) block order.  Blocks are taken four
+// at a time along a row's z run; the potential loads of the next four are
+// issued before the current four are used, so that their latency overlaps
+// the arithmetic.  body(f, xa, ya, za): f = v(r) exp(-alpha_p |r-P|^2) inside
+// the sphere, else 0; (xa, ya, za) = r - A.
 template <typename T, typename Body>
-__device__ __forceinline__ void for_each_point(const PairRec &r, const LevelGeom &G, const T *te, const T *td,
-                                               int wmax, const AxisBlock *bl, int emax, const int *cnt,
+__device__ __forceinline__ void for_each_point(const PairRec &r, const T *te, const T *td, int wmax,
+                                               const AxisBlock *bl, int emax, const BlockRow *rows, int nrows,
                                                const double *__restrict__ Vb, Body &&body)
 {
     const int lane = threadIdx.x;
     const int tx = lane >> 4, ty = (lane >> 2) & 3, tz = lane & 3;
-    const double R2c = r.R2 * kCullSlack;
     const T ER = (T)r.ER;
-    const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]);
-    const AxisBlock *blx = bl, *bly = bl + emax, *blz = bl + 2 * emax;
-    for (int ex = 0; ex < nx; ++ex) {
-        const double gx = uni(blx[ex].gap2);
-        if (gx > R2c) continue;
-        const int jx = blx[ex].j0 + tx;
-        const int kx = uni(blx[ex].k);
-        const T exv = te[jx], xa = td[jx];
-        for (int ey = 0; ey < ny; ++ey) {
-            const double gxy = gx + uni(bly[ey].gap2);
-            if (gxy > R2c) continue;
-            const int jy = bly[ey].j0 + ty;
-            const int ky = uni(bly[ey].k);
-            const T exy = exv * te[wmax + jy], ya = td[wmax + jy];
-            const long long bxy = ((long long)kx * G.nb[1] + ky) * G.nb[2];
-            const double rem = R2c - gxy;
-            int zlo = 0, zhi = nz - 1;
-            while (zlo < nz && uni(blz[zlo].gap2) > rem) ++zlo;
-            while (zhi >= zlo && uni(blz[zhi].gap2) > rem) --zhi;
-            // the run of z blocks meeting the sphere, four at a time: the four
-            // potential loads are issued together before any is used
-            for (int ez = zlo; ez <= zhi; ez += 4) {
-                int kz[4], jz[4];
+    const AxisBlock *blz = bl + 2 * emax;
+    if (nrows <= 0) return;
+    // cursor: row index rr, first z entry ez of the batch
+    int rr = 0;
+    BlockRow row = rows[0];
+    int zhi = uni(row.zz) >> 16;
+    int ez = uni(row.zz) & 0xffff;
+    double vv[4];
+    int jz[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = ez + u <= zhi ? ez + u : zhi;
-                    kz[u] = uni(blz[e].k);
-                    jz[u] = blz[e].j0 + tz;
-                }
-                double vv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) vv[u] = Vb[(bxy + kz[u]) * 64 + lane];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (ez + u <= zhi) {
-                        const T E = exy * te[2 * wmax + jz[u]];
-                        body((E >= ER) ? (T)vv[u] * E : T(0), xa, ya, td[2 * wmax + jz[u]]);
-                    }
-                }
+    for (int u = 0; u < 4; ++u) {
+        const int e = ez + u <= zhi ? ez + u : zhi;
+        vv[u] = Vb[((long long)uni(row.bxy) + uni(blz[e].k)) * 64 + lane];
+    }
+    for (;;) {
+        // next batch: the rest of this row's run, else the next row
+        int nrr = rr, nez = ez + 4, nzhi = zhi;
+        BlockRow nrow = row;
+        if (nez > zhi) {
+            nrr = rr + 1;
+            if (nrr < nrows) {
+                nrow = rows[nrr];
+                nez = uni(nrow.zz) & 0xffff;
+                nzhi = uni(nrow.zz) >> 16;
             }
         }
+        const bool more = nrr < nrows;
+        double vn[4];
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = nez + u <= nzhi ? nez + u : nzhi;
+                vn[u] = Vb[((long long)uni(nrow.bxy) + uni(blz[e].k)) * 64 + lane];
+            }
+        }
+        const int jx = row.jx0 + tx, jy = row.jy0 + ty;
+        const T xa = td[jx], ya = td[wmax + jy];
+        const T exy = te[jx] * te[wmax + jy];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) jz[u] = blz[ez + u <= zhi ? ez + u : zhi].j0 + tz;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (ez + u <= zhi) {
+                const T E = exy * te[2 * wmax + jz[u]];
+                body((E >= ER) ? (T)vv[u] * E : T(0), xa, ya, td[2 * wmax + jz[u]]);
+            }
+        }
+        if (!more) break;
+        rr = nrr;
+        row = nrow;
+        ez = nez;
+        zhi = nzhi;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) vv[u] = vn[u];
     }
 }
 
 // LDS layout of the pair-major kernels: te[3][wmax], td[3][wmax] (T), then the
-// block lists bl[3][emax] and their counts.
+// block lists bl[3][emax], their counts and the block rows (at most emax^2).
 template <typename T>
 struct PairSmem {
     static __device__ __forceinline__ void carve(unsigned char *raw, int wmax, int emax, T *&te, T *&td,
-                                                 AxisBlock *&bl, int *&cnt)
+                                                 AxisBlock *&bl, int *&cnt, BlockRow *&rows)
     {
         te = reinterpret_cast<T *>(raw);
         td = te + 3 * wmax;
@@ -537,12 +592,13 @@ struct PairSmem {
         off = (off + 15) & ~size_t(15);
         bl = reinterpret_cast<AxisBlock *>(raw + off);
         cnt = reinterpret_cast<int *>(bl + 3 * emax);
+        rows = reinterpret_cast<BlockRow *>(cnt + 4);
     }
     static size_t bytes(int wmax, int emax)
     {
         size_t off = sizeof(T) * 6 * (size_t)wmax;
         off = (off + 15) & ~size_t(15);
-        return off + sizeof(AxisBlock) * 3 * (size_t)emax + 16;
+        return off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)emax * emax;
     }
 };
 
@@ -555,6 +611,7 @@ k_mat(SegTable<PairSeg> tab)
     T *te, *td;
     AxisBlock *bl;
     int *cnt;
+    BlockRow *rows;
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
@@ -562,15 +619,17 @@ k_mat(SegTable<PairSeg> tab)
     const int wmax = sg.wmax, n_ao = sg.n_ao;
     const double *__restrict__ Vb = sg.Vb;
     const int emax = wmax / 4 + 3;
-    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt);
+    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
     pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
+    __syncthreads();
+    const int nrows = build_rows(r.R2 * kCullSlack, G, bl, emax, cnt, rows);
     __syncthreads();
     T acc[NA * NB];
 #pragma unroll
     for (int i = 0; i < NA * NB; ++i) acc[i] = T(0);
     const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
-    for_each_point<T>(r, G, te, td, wmax, bl, emax, cnt, Vb, [&](T f, T xa, T ya, T za) {
+    for_each_point<T>(r, te, td, wmax, bl, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za) {
         T a[NA], bb[NB];
         monomials<LA, T>(xa, ya, za, a);
         monomials<LB, T>(xa + abx, ya + aby, za + abz, bb);
@@ -603,6 +662,7 @@ k_grad(SegTable<PairSeg> tab)
     T *te, *td;
     AxisBlock *bl;
     int *cnt;
+    BlockRow *rows;
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
@@ -610,15 +670,17 @@ k_grad(SegTable<PairSeg> tab)
     const int wmax = sg.wmax, n_ao = sg.n_ao;
     const double *__restrict__ Vb = sg.Vb;
     const int emax = wmax / 4 + 3;
-    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt);
+    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
     pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
+    __syncthreads();
+    const int nrows = build_rows(r.R2 * kCullSlack, G, bl, emax, cnt, rows);
     __syncthreads();
     T gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
     const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
     const T two_aa = (T)(2.0 * r.aa), two_ab = (T)(2.0 * r.ab);
     const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
-    for_each_point<T>(r, G, te, td, wmax, bl, emax, cnt, Vb, [&](T f, T xa, T ya, T za) {
+    for_each_point<T>(r, te, td, wmax, bl, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za) {
         const T xb = xa + abx, yb = ya + aby, zb = za + abz;
         T a[NA], bb[NB], t[NA], sv[NB];
         monomials<LA, T>(xa, ya, za, a);

@@ -283,3 +283,17 @@ def test_mesh_rule_hand_values():
         s = synth.water_cluster(1, L, 1, synth.O_BASIS_SMALL)
         o = oracle.Oracle(s)
         assert [m[0] for m in o.meshes] == expect
+
+
+def test_mask_either_gives_complete_gradient_rows():
+    """The sampling filter: with pairs that touch the selected atoms, their
+    gradient rows equal those of the full sum."""
+    s = tiny.subset_waters(synth.config3(tau=1e-12), 3)
+    o = oracle.Oracle(s)
+    D = synth.make_density(s)
+    V = synth.make_potentials(o.meshes, 5)
+    g = o.grad(D, V)
+    mask = np.zeros(s.natm, dtype=np.uint8)
+    mask[[1, 5]] = 1
+    gm = oracle.Oracle(s, atom_mask=mask, mask_either=True).grad(D, V)
+    assert np.abs(gm[[1, 5]] - g[[1, 5]]).max() < 1e-12 * np.abs(g).max()
