@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--cpu-atoms", type=int, default=0, help="atoms in the oracle sample (0 = auto)")
     ap.add_argument("--extras", type=int, default=1, help="also time grad, fp32 and the plan")
     ap.add_argument("--serve-requests", type=int, default=120, help="requests in the serving run (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-rates", default="20,100", help="Poisson arrival rates (requests/s), comma-separated")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters) and exit")
@@ -134,10 +134,11 @@ def fp32_errors():
             "grad_rel_err": float((F32 - F64).abs().max() / F64.abs().max())}
 
 
-def serving(n, rate, budget_gb):
+def serving(n, rates, budget_gb):
     """Poisson arrivals of mixed Fock / gradient requests on water-like
     clusters of 8..256 units (two geometries each): continuous batching vs
-    one-at-a-time plain calls on the same trace and resident plans."""
+    one-at-a-time plain calls on the same trace and resident plans, per
+    arrival rate."""
     from paper_2603_24881_amd import synth
     from paper_2603_24881_amd.serve import GPUExecutor, Scheduler, poisson_trace, summarize, system_key
     sizes = (8, 16, 32, 64, 128, 256)
@@ -148,20 +149,23 @@ def serving(n, rate, budget_gb):
             ex.register(system_key(nw, geo), synth.config5(nw, geo))
     reg = time.perf_counter() - t0
     log(f"[bench] serving: 12 plans registered in {reg:.1f} s")
-    out = {"rate_per_s": rate, "requests": n, "sizes_waters": list(sizes), "geometries": 2,
-           "budget_gb": budget_gb, "plan_register_s": round(reg, 2)}
-    warm = poisson_trace(12, 1000.0, seed=1999)
+    out = {"requests": n, "sizes_waters": list(sizes), "geometries": 2, "grad_fraction": 0.5,
+           "budget_gb": budget_gb, "max_active": 16, "plan_register_s": round(reg, 2), "runs": []}
+    warm = poisson_trace(24, 1000.0, seed=1999)
     Scheduler(ex, budget_gb * 2 ** 30).run(warm)
-    for mode in ("continuous", "sequential"):
-        trace = poisson_trace(n, rate, seed=2000)
-        sch = Scheduler(ex, budget_gb * 2 ** 30)
-        (sch.run if mode == "continuous" else sch.run_sequential)(trace)
-        sm = summarize(trace)
-        if mode == "continuous":
-            sm["rounds"] = len(sch.rounds)
-            sm["mean_tasks_per_round"] = float(np.mean([a + b for a, b in sch.rounds]))
-        out[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
-        log(f"[bench] serving {mode}: {out[mode]}")
+    for rate in rates:
+        run = {"rate_per_s": rate}
+        for mode in ("continuous", "sequential"):
+            trace = poisson_trace(n, rate, seed=2000)
+            sch = Scheduler(ex, budget_gb * 2 ** 30)
+            (sch.run if mode == "continuous" else sch.run_sequential)(trace)
+            sm = summarize(trace)
+            if mode == "continuous":
+                sm["rounds"] = len(sch.rounds)
+                sm["mean_tasks_per_round"] = float(np.mean([a + b for a, b in sch.rounds]))
+            run[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
+            log(f"[bench] serving {rate:g}/s {mode}: {run[mode]}")
+        out["runs"].append(run)
     return out
 
 
@@ -273,7 +277,8 @@ def main():
     if args.serve_requests > 0:
         del rho, M, V, D
         torch.cuda.empty_cache()
-        out["serving"] = serving(args.serve_requests, args.serve_rate, args.serve_budget_gb)
+        out["serving"] = serving(args.serve_requests, [float(x) for x in args.serve_rates.split(",")],
+                                 args.serve_budget_gb)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)...")
         out["cpu_baseline"] = cpu_baseline(system, Dn, V_np, args.cpu_atoms, info)

@@ -53,6 +53,10 @@
  * later call.  On error the outputs are unspecified and the plan stays valid.
  * gpw_last_error() returns a thread-local message for the last failure.
  *
+ * Scratch: eval calls take temporary device memory from the device's default
+ *   stream-ordered pool (hipMallocAsync) and return it on the same stream;
+ *   gpw_plan sets that pool's release threshold to "keep everything", so the
+ *   pool retains its peak size for the life of the process.
  * Streams: eval calls enqueue on the given hipStream_t (NULL = the default
  * stream) and return without synchronising.  Inputs must stay valid and
  * outputs untouched until the stream reaches the end of the call.  One plan

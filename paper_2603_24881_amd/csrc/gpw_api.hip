@@ -182,6 +182,16 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
 
     DeviceGuard guard(pl->device);
     if (guard.err != hipSuccess) { free_plan(pl); return hip_fail(guard.err, "gpw_plan: hipSetDevice"); }
+    {
+        // The eval calls take their scratch from the device's default stream-ordered
+        // pool; keep freed blocks in the pool instead of returning them to the driver
+        // at every synchronisation, so that repeated evaluations do not remap memory.
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, pl->device) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     hipStream_t st = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e != hipSuccess) { free_plan(pl); return hip_fail(e, "gpw_plan: hipStreamCreate"); }

@@ -66,7 +66,7 @@ struct RhoSeg {
     const RhoRec *rr;            // records of the (level, class) group
     const int2 *inc;             // (pair image, shift) entries
     const long long *inc_off;    // CSR offsets of the group's blocks
-    const int *blk;              // nonempty blocks of the group
+    const int *blk;              // slots of the group's nonempty blocks
     const void *Dpk;             // packed D sub-blocks of the group
     double *rho;                 // level grid
     int p0;                      // plan index of the group's first pair image
@@ -302,10 +302,9 @@ k_rho(SegTable<RhoSeg> tab)
     const int2 *__restrict__ inc = sg.inc;
     const T *__restrict__ Dpk = (const T *)sg.Dpk;
     const int p0 = sg.p0;
-    const int b = sg.blk[item];
-    const int kz = b % G.nb[2];
-    const int ky = (b / G.nb[2]) % G.nb[1];
-    const int kx = b / (G.nb[2] * G.nb[1]);
+    const int b = sg.blk[item];   // block slot
+    int kx, ky, kz;
+    slot_block(G, b, kx, ky, kz);
     const int kk[3] = {kx, ky, kz};
     const long long s0 = sg.inc_off[b], s1 = sg.inc_off[b + 1];
     const RhoRec *rr = sg.rr;

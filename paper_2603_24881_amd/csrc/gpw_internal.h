@@ -66,6 +66,37 @@ struct LevelGeom {
     double w;         // quadrature weight Omega / N_l
 };
 
+// Slot of a 4x4x4 block in the per-group incidence lists: tiles of 8x8x8
+// blocks in row-major order, Morton (z-order) inside a tile, so that a run
+// of consecutive slots is a compact region of space (neighbouring blocks
+// share most of their pair images).  Slots of padding blocks of partial
+// tiles stay empty.
+__host__ __device__ inline int spread3(int v)   // 3 bits -> bits 0, 3, 6
+{
+    return (v & 1) | ((v & 2) << 2) | ((v & 4) << 4);
+}
+__host__ __device__ inline int gather3(int v) { return (v & 1) | ((v >> 2) & 2) | ((v >> 4) & 4); }
+__host__ __device__ inline long long block_slot(const LevelGeom &G, int kx, int ky, int kz)
+{
+    const int ty = (G.nb[1] + 7) >> 3, tz = (G.nb[2] + 7) >> 3;
+    const long long tile = ((long long)(kx >> 3) * ty + (ky >> 3)) * tz + (kz >> 3);
+    return tile * 512 + ((spread3(kx & 7) << 2) | (spread3(ky & 7) << 1) | spread3(kz & 7));
+}
+__host__ __device__ inline void slot_block(const LevelGeom &G, long long slot, int &kx, int &ky, int &kz)
+{
+    const int ty = (G.nb[1] + 7) >> 3, tz = (G.nb[2] + 7) >> 3;
+    const long long tile = slot >> 9;
+    const int m = (int)(slot & 511);
+    const int tkz = (int)(tile % tz), tky = (int)((tile / tz) % ty), tkx = (int)(tile / ((long long)tz * ty));
+    kx = tkx * 8 + gather3(m >> 2);
+    ky = tky * 8 + gather3(m >> 1);
+    kz = tkz * 8 + gather3(m);
+}
+inline long long block_slots(const LevelGeom &G)
+{
+    return (long long)((G.nb[0] + 7) >> 3) * ((G.nb[1] + 7) >> 3) * ((G.nb[2] + 7) >> 3) * 512;
+}
+
 // Incidence entry: pair index and the fold shifts (unwrapped = wrapped + S*N).
 __host__ __device__ inline int pack_shift(int sx, int sy, int sz)
 {

@@ -162,7 +162,7 @@ k_incidences(const PairRec *pairs, long long npairs, PlanConst pc, const long lo
                 double z0, z1;
                 iz.range(G.h[2], z0, z1);
                 if (gy + axis_gap2(r.P[2], z0, z1) > R2c) continue;
-                const long long b = (ix.k * G.nb[1] + iy.k) * G.nb[2] + iz.k;
+                const long long b = block_slot(G, (int)ix.k, (int)iy.k, (int)iz.k);
                 if (ix.S < -127 || ix.S > 127 || iy.S < -127 || iy.S > 127 || iz.S < -127 || iz.S > 127) {
                     atomicOr(err_flag, 2);   // fold shift does not fit the packed entry
                     continue;
@@ -372,7 +372,7 @@ __global__ void k_flags(const unsigned *cnt, long long n, unsigned *flags)
     if (i < n) flags[i] = cnt[i] ? 1u : 0u;
 }
 
-// compacted block list: for every counter with entries, its block id in the level
+// compacted block list: for every counter with entries, its block slot in the level
 __global__ void k_compact_blocks(const unsigned *cnt, long long n, const long long *flag_off,
                                  const long long *cnt_base_g, int ngroups, int *blk)
 {
@@ -463,11 +463,11 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         PCHK(hipGetLastError());
     }
 
-    // counters per (group, block)
+    // counters per (group, block slot)
     long long ncnt = 0;
     for (int g = 0; g <= kMaxGroups; ++g) {
         pl->cnt_base[g] = ncnt;
-        if (g < ngroups) ncnt += pl->nblocks[g / kNCls];
+        if (g < ngroups) ncnt += block_slots(pl->geom[g / kNCls]);
     }
     long long *d_cnt_base = nullptr;
     unsigned *d_cnt = nullptr, *d_cur = nullptr, *d_flags = nullptr;

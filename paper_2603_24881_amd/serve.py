@@ -196,8 +196,9 @@ def summarize(requests):
 
 class GPUExecutor:
     """Runs requests on one device through the C ABI.  Plans and their
-    Poisson tables are built at ``register`` (their size is then known) and
-    stay resident until the scheduler unloads them."""
+    Poisson tables are built at ``register`` (their size is then known, and
+    the FFT plans of their meshes are warmed up) and stay resident until the
+    scheduler unloads them."""
 
     def __init__(self, device=0, precision="fp64", keep_results=False):
         import torch
@@ -217,6 +218,9 @@ class GPUExecutor:
         self.systems[key] = system
         g = GPW(system, precision=self.precision, device=self.device)
         p = g.poisson()
+        # the first FFT of a mesh size builds (and compiles) its FFT plans,
+        # which can take seconds: do it here, not in a request's latency
+        p.solve([self.torch.zeros(tuple(m), dtype=self.torch.float64, device=self.dev) for m in g.meshes])
         info = g.info
         fine = int(np.prod(info["mesh"][0]))
         ngrid = sum(int(np.prod(m)) for m in info["mesh"])
