@@ -79,7 +79,7 @@ struct PairSeg {
     const void *Dm;              // grad: symmetrised D
     const double *Vb;            // block-ordered level potential
     double *out;                 // mat: M; grad: natm x 3
-    int n_ao, wmax;
+    int n_ao, wmax, emax;
     LevelGeom G;
 };
 
@@ -411,7 +411,8 @@ __device__ __forceinline__ double uni(double v)
 
 // LDS set-up of one pair image: 1-D tables over u in [lo-3, hi+3] per axis
 // (envelope exp(-alpha_p (x_u - P)^2) and offset x_u - A) and the per-axis
-// lists of the blocks (with fold shifts) its bounding box meets.
+// lists of the blocks (with fold shifts) its bounding box meets, one entry per
+// lane.  emax bounds every list (the plan's longest).
 template <typename T>
 __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G, T *te, T *td, int wmax,
                                            AxisBlock *bl, int emax, int *cnt)
@@ -426,21 +427,24 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             td[d * wmax + i] = (T)(x - r.A[d]);
         }
     }
-    if (threadIdx.x < 3) {
-        const int d = threadIdx.x;
-        AxisIter it;
-        int n = 0;
-        for (it.start(r.lo[d], r.hi[d], G.N[d], G.nb[d]); it.valid() && n < emax; it.next()) {
-            double x0, x1;
-            it.range(G.h[d], x0, x1);
-            AxisBlock e;
-            e.k = (int)it.k;
-            e.j0 = (int)(4 * it.k + it.S * G.N[d]) - (r.lo[d] - 3);
-            e.gap2 = axis_gap2(r.P[d], x0, x1);
-            bl[d * emax + n] = e;
-            ++n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int N = G.N[d], nb = G.nb[d];
+        const int g0 = axis_block_id(r.lo[d], N, nb);
+        const int n = axis_block_count(r.lo[d], r.hi[d], N, nb);
+        for (int e = threadIdx.x; e < n; e += 64) {
+            const int gi = g0 + e;
+            const int S = floordiv(gi, nb);
+            const int k = gi - S * nb;
+            const int u0 = 4 * k + S * N;
+            const int u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
+            AxisBlock eb;
+            eb.k = k;
+            eb.j0 = u0 - (r.lo[d] - 3);
+            eb.gap2 = axis_gap2(r.P[d], (double)u0 * G.h[d], (double)u1 * G.h[d]);
+            bl[d * emax + e] = eb;
         }
-        cnt[d] = n;
+        if (threadIdx.x == 0) cnt[d] = n;
     }
 }
 
@@ -533,7 +537,8 @@ __device__ __forceinline__ void for_each_point(const PairRec &r, const T *te, co
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int e = ez + u <= zhi ? ez + u : zhi;
-        vv[u] = Vb[((long long)uni(row.bxy) + uni(blz[e].k)) * 64 + lane];
+        const double *vb = Vb + ((long long)uni(row.bxy) + uni(blz[e].k)) * 64;   // uniform
+        vv[u] = vb[lane];
     }
     for (;;) {
         // next batch: the rest of this row's run, else the next row
@@ -553,7 +558,8 @@ __device__ __forceinline__ void for_each_point(const PairRec &r, const T *te, co
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = nez + u <= nzhi ? nez + u : nzhi;
-                vn[u] = Vb[((long long)uni(nrow.bxy) + uni(blz[e].k)) * 64 + lane];
+                const double *vb = Vb + ((long long)uni(nrow.bxy) + uni(blz[e].k)) * 64;
+                vn[u] = vb[lane];
             }
         }
         const int jx = row.jx0 + tx, jy = row.jy0 + ty;
@@ -615,9 +621,8 @@ k_mat(SegTable<PairSeg> tab)
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const LevelGeom &G = sg.G;
-    const int wmax = sg.wmax, n_ao = sg.n_ao;
+    const int wmax = sg.wmax, n_ao = sg.n_ao, emax = sg.emax;
     const double *__restrict__ Vb = sg.Vb;
-    const int emax = wmax / 4 + 3;
     PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
     pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
@@ -666,9 +671,8 @@ k_grad(SegTable<PairSeg> tab)
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const LevelGeom &G = sg.G;
-    const int wmax = sg.wmax, n_ao = sg.n_ao;
+    const int wmax = sg.wmax, n_ao = sg.n_ao, emax = sg.emax;
     const double *__restrict__ Vb = sg.Vb;
-    const int emax = wmax / 4 + 3;
     PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
     pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
@@ -788,7 +792,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
 {
     std::vector<TaskScratch> ts(n);
     size_t bytes = 0;
-    int wmax_all = 8;
+    int wmax_all = 8, emax_all = 1;
     for (int i = 0; i < n; ++i) {
         const TaskRef &t = tasks[i];
         const gpw_plan_s *pl = t.pl;
@@ -811,6 +815,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
             x.vb = bytes;
             bytes += align256(sizeof(double) * (size_t)tot);
             wmax_all = std::max(wmax_all, pl->info.max_box_width + 8);
+            emax_all = std::max(emax_all, pl->max_axis_blocks);
             if (t.op == GPW_OP_GRAD) {
                 x.ds = bytes;
                 bytes += align256(sizeof(T) * (size_t)pl->n_ao * pl->n_ao);
@@ -861,6 +866,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
             const TaskRef &t = tasks[i];
             const gpw_plan_s *pl = t.pl;
             const int wmax = pl->info.max_box_width + 8;
+            const int emax = std::max(1, pl->max_axis_blocks);
             for (int l = 0; l < pl->nlevels; ++l) {
                 const int g = l * kNCls + c;
                 const long long np = pl->group_off[g + 1] - pl->group_off[g];
@@ -891,12 +897,13 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
                     q.out = t.out;
                     q.n_ao = pl->n_ao;
                     q.wmax = wmax;
+                    q.emax = emax;
                     q.G = pl->geom[l];
                     (t.op == GPW_OP_MAT ? mats : grads).add(q, np);
                 }
             }
         }
-        const size_t smem = PairSmem<T>::bytes(wmax_all, wmax_all / 4 + 3);
+        const size_t smem = PairSmem<T>::bytes(wmax_all, emax_all);
         dispatch_cls(c, [&](auto la, auto lb) {
             constexpr int LA = decltype(la)::value, LB = decltype(lb)::value;
             constexpr int NA = ncart_c(LA), NB = ncart_c(LB);

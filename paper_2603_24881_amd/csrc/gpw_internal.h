@@ -175,6 +175,22 @@ struct AxisIter {
     }
 };
 
+// The 4-point blocks (with their fold shifts) that an unwrapped index range
+// [lo, hi] of one axis meets, in increasing order of the unwrapped index: the
+// unwrapped index u lies in block k = (u - S N) / 4 of period S = floor(u / N);
+// numbered g(u) = S nb + k these blocks form the contiguous range
+// [g(lo), g(hi)] (g grows by at most one per index), so entry e of the list
+// is g(lo) + e.  The same list as AxisIter, in closed form.
+__device__ inline int axis_block_id(int u, int N, int nb)
+{
+    const int S = floordiv(u, N);
+    return S * nb + (u - S * N) / 4;
+}
+__device__ inline int axis_block_count(int lo, int hi, int N, int nb)
+{
+    return hi < lo ? 0 : axis_block_id(hi, N, nb) - axis_block_id(lo, N, nb) + 1;
+}
+
 // Work item of this workgroup such that each of the 8 XCDs (workgroups are
 // dealt to them round robin) walks one contiguous eighth of a list of n items;
 // the grid holds 8 * ceil(n / 8) workgroups and items >= n do nothing.
@@ -246,6 +262,7 @@ struct gpw_plan_s {
     long long blk_off[gpw::kMaxGroups + 1] = {};
 
     gpw_plan_info info{};
+    int max_axis_blocks = 0;   // longest per-axis block list of a pair image
     std::vector<void *> allocations;
 };
 

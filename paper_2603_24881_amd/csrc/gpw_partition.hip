@@ -194,9 +194,13 @@ k_incidences(const PairRec *pairs, long long npairs, PlanConst pc, const long lo
                 if (z1 >= z0) npts += z1 - z0 + 1;
             }
         }
-        int w = 0;
-        for (int d = 0; d < 3; ++d) w = max(w, r.hi[d] - r.lo[d] + 1);
-        atomicMax(maxw, w);
+        int w = 0, nbl = 0;
+        for (int d = 0; d < 3; ++d) {
+            w = max(w, r.hi[d] - r.lo[d] + 1);
+            nbl = max(nbl, axis_block_count(r.lo[d], r.hi[d], G.N[d], G.nb[d]));
+        }
+        atomicMax(&maxw[0], w);
+        atomicMax(&maxw[1], nbl);
         atomicAdd(&stats[2 * g + 0], (double)npts);
         atomicAdd(&stats[2 * g + 1], (double)ninc);
     }
@@ -474,8 +478,8 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     long long *d_flag_off = nullptr;
     double *d_stats = nullptr;
     int *d_maxw = nullptr;
-    PCHK(hipMalloc(&d_maxw, sizeof(int)));
-    PCHK(hipMemsetAsync(d_maxw, 0, sizeof(int), st));
+    PCHK(hipMalloc(&d_maxw, 2 * sizeof(int)));
+    PCHK(hipMemsetAsync(d_maxw, 0, 2 * sizeof(int), st));
     PCHK(hipMalloc(&d_cnt_base, sizeof(long long) * (kMaxGroups + 1)));
     PCHK(hipMemcpyAsync(d_cnt_base, pl->cnt_base, sizeof(long long) * (kMaxGroups + 1), hipMemcpyHostToDevice, st));
     PCHK(hipMalloc(&d_cnt, sizeof(unsigned) * (size_t)(ncnt + 1)));
@@ -530,10 +534,12 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     }
     double stats[2 * kMaxGroups];
     PCHK(hipMemcpyAsync(stats, d_stats, sizeof(stats), hipMemcpyDeviceToHost, st));
-    int maxw = 0, errf = 0;
-    PCHK(hipMemcpyAsync(&maxw, d_maxw, sizeof(int), hipMemcpyDeviceToHost, st));
+    int maxwb[2] = {0, 0}, errf = 0;
+    PCHK(hipMemcpyAsync(maxwb, d_maxw, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     PCHK(hipMemcpyAsync(&errf, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
     PCHK(hipStreamSynchronize(st));
+    const int maxw = maxwb[0];
+    pl->max_axis_blocks = maxwb[1];
     for (int g = 0; g <= kMaxGroups; ++g) pl->blk_off[g] = flag_at[g];
     if (errf & 1) { err = "partitioner count and fill passes disagree"; return hipErrorUnknown; }
     if (errf & 2) { err = "a truncation sphere reaches beyond 127 cells (fold shift out of range)"; return hipErrorInvalidValue; }
