@@ -72,6 +72,28 @@ def timed(fn, steps, stream):
     return start.elapsed_time(end) / 1e3 / steps
 
 
+def measured_traffic(op):
+    """HBM bytes per evaluation of ``op`` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "eval_rho_eval_mat_water256_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()[:2]
+        vals[k] = v
+    h = hashlib.sha256()
+    for fn in ("gpw_eval.hip", "gpw_partition.hip", "gpw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2603_24881_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    if vals.get("source_sha256") != h.hexdigest() or f"{op}_bytes" not in vals:
+        return None
+    return int(vals[f"{op}_bytes"])
+
+
 def cpu_baseline(system, D_np, V_np, natoms_hint, info):
     """The oracle on a bounded sample: the ordered pair images whose first
     primitive sits on the first ``n`` atoms; rho and mat.  Its rate is stated
@@ -80,7 +102,7 @@ def cpu_baseline(system, D_np, V_np, natoms_hint, info):
     in-sphere work of the job) of the job, and value = that fraction of the
     job's block flops per second of oracle time."""
     import oracle
-    n = natoms_hint or max(3, int(round(system.natm * 0.15)))
+    n = natoms_hint or max(3, int(round(system.natm * 0.30)))
     mask = np.zeros(system.natm, dtype=np.uint8)
     mask[:n] = 1
     o = oracle.Oracle(system, atom_mask=mask)
@@ -225,9 +247,10 @@ def main():
     log(f"[bench] step {t_step * 1e3:.2f} ms (rho {t_rho * 1e3:.2f} ms, mat {t_mat * 1e3:.2f} ms), "
         f"{value:.0f} GFLOP/s block work, {(f_rho_s + f_mat_s) / t_step / 1e9:.0f} GFLOP/s in-sphere")
     if t_rho >= t_mat:
-        dom, dt, fl = "k_rho (density collocation, all classes and levels of one eval_rho)", t_rho, f_rho_b
+        dom, dt, fl, op = "k_rho (density collocation, all classes and levels of one eval_rho)", t_rho, f_rho_b, "eval_rho"
     else:
-        dom, dt, fl = "k_mat (potential integration, all classes and levels of one eval_mat)", t_mat, f_mat_b
+        dom, dt, fl, op = "k_mat (potential integration, all classes and levels of one eval_mat)", t_mat, f_mat_b, "eval_mat"
+    traffic = measured_traffic(op) if args.workload == "water256" else None
     out = {
         "metric": "eval_rho+eval_mat FP64 GFLOP/s & %peak; served requests/s + p50/p99 latency",
         "value": round(value, 2),
@@ -245,7 +268,7 @@ def main():
                    "mesh": info["mesh"], "rel_cutoff_ry": system.rel_cutoff_ry},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(fl / dt / 1e12, 3),
                      "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": round(fl / dt / PEAK_FP64, 4),
-                     "traffic": None},
+                     "traffic": traffic},
         "pct_fp64_peak": round(100 * value * 1e9 / PEAK_FP64, 2),
         "ms_rho": round(t_rho * 1e3, 4),
         "ms_mat": round(t_mat * 1e3, 4),

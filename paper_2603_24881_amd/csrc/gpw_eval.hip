@@ -381,7 +381,7 @@ k_rho(SegTable<RhoSeg> tab)
 
 // register-budget split of the rho kernel per class: {NPASS, waves/SIMD}
 template <int LA, int LB> struct RhoSplit { static constexpr int npass = 1, wpe = 2; };
-template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, wpe = 1; };
+template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, wpe = 2; };
 template <> struct RhoSplit<2, 0> { static constexpr int npass = 1, wpe = 1; };
 template <> struct RhoSplit<2, 1> { static constexpr int npass = 1, wpe = 1; };
 template <> struct RhoSplit<2, 2> { static constexpr int npass = 2, wpe = 1; };
