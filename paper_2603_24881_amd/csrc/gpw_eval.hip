@@ -232,9 +232,18 @@ __device__ __forceinline__ void reduce_points(const T *acc, double (*red)[65], i
     }
 }
 
+// Elements per packed D sub-block: n_a n_b padded to a multiple of 16 bytes
+// (the rho kernel copies sub-blocks in 16-byte pieces).
+template <typename T>
+__host__ __device__ constexpr int dstride(int na, int nb)
+{
+    return (na * nb * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
+}
+
 // Kw-scaled, symmetrised D sub-blocks of every pair image of one (level,
-// class) group, packed per pair image (n_a n_b values each), so that the rho
-// kernel reads a pair image's D and geometry in one round of loads.
+// class) group, packed per pair image (n_a n_b values each, padded to 16
+// bytes), so that the rho kernel reads a pair image's D and geometry in one
+// round of loads.
 template <typename T, int NA, int NB>
 __global__ void __launch_bounds__(256)
 k_pack_density(SegTable<PackSeg> tab)
@@ -250,16 +259,39 @@ k_pack_density(SegTable<PackSeg> tab)
     const int i = ij / NB, j = ij % NB;
     const PairRec &r = sg.pairs[lp];
     const long long a = r.ao_a + i, b = r.ao_b + j;
-    out[e] = (T)(r.Kw * 0.5 * (D[a * n + b] + D[b * n + a]));
+    out[lp * dstride<T>(NA, NB) + ij] = (T)(r.Kw * 0.5 * (D[a * n + b] + D[b * n + a]));
 }
 
-// Per-lane state of one pair image in the rho kernel.
+// Per-lane state of one pair image in the rho kernel.  The record and the D
+// sub-block of the next batch are copied from global memory straight into
+// LDS (16-byte direct-to-LDS loads, one instruction per 16-byte piece for
+// the whole wave, piece c of lane l at c * 1024 + l * 16), so the copy needs
+// no registers while the current batch is computed.
 template <typename T, int NA, int NB>
 struct RhoLane {
+    static constexpr int DB = dstride<T>(NA, NB) * (int)sizeof(T);   // bytes of a D sub-block
+    static constexpr int NCH = 8 + DB / 16;                          // 16-byte pieces per lane
+    static constexpr int STAGE = NCH * 1024;                         // LDS bytes of a batch
     double A[3], AB[3], P[3], c[3];
     double ap, ER;
     T Dk[NA * NB];
-    __device__ __forceinline__ void load(const RhoRec *__restrict__ rr, const T *__restrict__ Dpk, int lp)
+    static __device__ __forceinline__ void stage(const RhoRec *__restrict__ rr, const T *__restrict__ Dpk, int lp,
+                                                 unsigned char *lds)
+    {
+        const unsigned char *gr = reinterpret_cast<const unsigned char *>(rr + lp);
+        const unsigned char *gd = reinterpret_cast<const unsigned char *>(Dpk + (long long)lp * dstride<T>(NA, NB));
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            __builtin_amdgcn_global_load_lds((const void *)(gr + 16 * k),
+                                             (__attribute__((address_space(3))) void *)(lds + k * 1024), 16, 0, 0);
+#pragma unroll
+        for (int k = 0; k < DB / 16; ++k)
+            __builtin_amdgcn_global_load_lds((const void *)(gd + 16 * k),
+                                             (__attribute__((address_space(3))) void *)(lds + (8 + k) * 1024), 16, 0,
+                                             0);
+    }
+    // the same state straight from global memory (classes that do not stage)
+    __device__ __forceinline__ void load_global(const RhoRec *__restrict__ rr, const T *__restrict__ Dpk, int lp)
     {
         const RhoRec &r = rr[lp];
 #pragma unroll
@@ -271,9 +303,32 @@ struct RhoLane {
         }
         ap = r.ap;
         ER = r.ER;
-        const T *src = Dpk + (long long)lp * (NA * NB);
+        const T *src = Dpk + (long long)lp * dstride<T>(NA, NB);
 #pragma unroll
         for (int k = 0; k < NA * NB; ++k) Dk[k] = src[k];
+    }
+    __device__ __forceinline__ void load(const unsigned char *lds, int lane)
+    {
+        double r[16];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double2 v = *reinterpret_cast<const double2 *>(lds + k * 1024 + lane * 16);
+            r[2 * k] = v.x;
+            r[2 * k + 1] = v.y;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            A[d] = r[d];          // RhoRec: A[3] AB[3] P[3] ap Kw ER c[3] pad
+            AB[d] = r[3 + d];
+            P[d] = r[6 + d];
+            c[d] = r[12 + d];
+        }
+        ap = r[9];
+        ER = r[11];
+        constexpr int PER = 16 / (int)sizeof(T);
+#pragma unroll
+        for (int k = 0; k < NA * NB; ++k)
+            Dk[k] = *reinterpret_cast<const T *>(lds + (8 + k / PER) * 1024 + lane * 16 + (k % PER) * sizeof(T));
     }
 };
 
@@ -283,17 +338,21 @@ struct RhoLane {
 // registers and accumulates its contributions to the block's points over the
 // whole list; one LDS transpose-reduction per block sums the lanes (instead of
 // a block reduction per point).  The loads of the next batch (list entries two
-// batches ahead, geometry and D one batch ahead) are issued before the current
-// batch is computed, so their latency hides behind the arithmetic.  NPASS
-// splits the 64 points to bound the accumulator registers.
-template <int LA, int LB, int NPASS, int WPE, typename T>
+// batches ahead; geometry and D one batch ahead, straight into LDS) are issued
+// before the current batch is computed, so their latency hides behind the
+// arithmetic.  NPASS splits the 64 points to bound the accumulator registers.
+template <int LA, int LB, int NPASS, int WPE, bool STG, typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_rho(SegTable<RhoSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     constexpr int NX = 4 / NPASS;
     constexpr int NP = 16 * NX;
-    __shared__ double red[32][65];
+    using Lane = RhoLane<T, NA, NB>;
+    constexpr int LDSB = STG && Lane::STAGE > 32 * 65 * 8 ? Lane::STAGE : 32 * 65 * 8;
+    // the batch staging area, and after the last batch the reduction buffer
+    __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
+    double(*red)[65] = reinterpret_cast<double(*)[65]>(lds);
     const int lane = threadIdx.x;
     const RhoSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
@@ -314,17 +373,32 @@ k_rho(SegTable<RhoSeg> tab)
         T acc[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i) acc[i] = T(0);
-        // the list entries of the next batch are loaded one batch ahead
+        // list entries two batches ahead, record and D one batch ahead (in LDS)
+        // (classes without staging: entries one batch ahead, record and D at
+        // the start of each batch)
         int2 en1 = inc[s0 + lane < s1 ? s0 + lane : s1 - 1];
+        int2 en2 = inc[s0 + 64 + lane < s1 ? s0 + 64 + lane : s1 - 1];
+        if constexpr (STG) {
+            asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+            Lane::stage(rr, Dpk, en1.x - p0, lds);
+        }
         for (long long s = s0; s < s1; s += 64) {
             const bool act = s + lane < s1;
             const int2 en = en1;
-            {
-                const long long q1 = s + 64 + lane;
-                en1 = inc[q1 < s1 ? q1 : s1 - 1];
+            Lane cur;
+            if constexpr (STG) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this batch's pieces are in LDS
+                cur.load(lds, lane);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); // read before the area is refilled
+                if (s + 64 < s1) Lane::stage(rr, Dpk, en2.x - p0, lds);
+            } else {
+                cur.load_global(rr, Dpk, en.x - p0);
             }
-            RhoLane<T, NA, NB> cur;
-            cur.load(rr, Dpk, en.x - p0);
+            en1 = en2;
+            {
+                const long long q2 = s + 128 + lane;
+                en2 = inc[q2 < s1 ? q2 : s1 - 1];
+            }
             double fx[4], fy[4], fz[4];
             const double x0 = (double)(4 * kk[0] + shift_of(en.y, 0) * G.N[0]) * G.h[0];
             const double y0 = (double)(4 * kk[1] + shift_of(en.y, 1) * G.N[1]) * G.h[1];
@@ -379,16 +453,17 @@ k_rho(SegTable<RhoSeg> tab)
     }
 }
 
-// register-budget split of the rho kernel per class: {NPASS, waves/SIMD}
-template <int LA, int LB> struct RhoSplit { static constexpr int npass = 1, wpe = 2; };
-template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, wpe = 2; };
-template <> struct RhoSplit<2, 0> { static constexpr int npass = 1, wpe = 1; };
-template <> struct RhoSplit<2, 1> { static constexpr int npass = 1, wpe = 1; };
-template <> struct RhoSplit<2, 2> { static constexpr int npass = 2, wpe = 1; };
-template <> struct RhoSplit<3, 0> { static constexpr int npass = 1, wpe = 1; };
-template <> struct RhoSplit<3, 1> { static constexpr int npass = 2, wpe = 1; };
-template <> struct RhoSplit<3, 2> { static constexpr int npass = 2, wpe = 1; };
-template <> struct RhoSplit<3, 3> { static constexpr int npass = 4, wpe = 1; };
+// per class: points per pass (NPASS), waves per SIMD, and whether the next
+// batch is staged in LDS (chosen by measurement on the 256-water system)
+template <int LA, int LB> struct RhoSplit { static constexpr int npass = 1, wpe = 2; static constexpr bool stage = false; };
+template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, wpe = 2; static constexpr bool stage = true; };
+template <> struct RhoSplit<2, 0> { static constexpr int npass = 1, wpe = 1; static constexpr bool stage = true; };
+template <> struct RhoSplit<2, 1> { static constexpr int npass = 1, wpe = 1; static constexpr bool stage = true; };
+template <> struct RhoSplit<2, 2> { static constexpr int npass = 2, wpe = 1; static constexpr bool stage = false; };
+template <> struct RhoSplit<3, 0> { static constexpr int npass = 1, wpe = 1; static constexpr bool stage = false; };
+template <> struct RhoSplit<3, 1> { static constexpr int npass = 2, wpe = 1; static constexpr bool stage = false; };
+template <> struct RhoSplit<3, 2> { static constexpr int npass = 2, wpe = 1; static constexpr bool stage = false; };
+template <> struct RhoSplit<3, 3> { static constexpr int npass = 4, wpe = 1; static constexpr bool stage = false; };
 
 // ----------------------------------------------- pair-major traversal (mat, grad)
 
@@ -801,8 +876,8 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
             x.dbase[0] = 0;
             for (int g = 0; g < kMaxGroups; ++g) {
                 const int c = g % kNCls;
-                x.dbase[g + 1] =
-                    x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) * ncart(cls_la(c)) * ncart(cls_lb(c));
+                x.dbase[g + 1] = x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) *
+                                                  dstride<T>(ncart(cls_la(c)), ncart(cls_lb(c)));
             }
             x.dpk = bytes;
             bytes += align256(sizeof(T) * (size_t)x.dbase[kMaxGroups]);
@@ -911,7 +986,9 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
                 hipLaunchKernelGGL((k_pack_density<T, NA, NB>), dim3(g), dim3(256), 0, st, tb);
             }, false);
             rhos.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
-                hipLaunchKernelGGL((k_rho<LA, LB, RhoSplit<LA, LB>::npass, RhoSplit<LA, LB>::wpe, T>), dim3(g),
+                hipLaunchKernelGGL((k_rho<LA, LB, RhoSplit<LA, LB>::npass, RhoSplit<LA, LB>::wpe,
+                                          RhoSplit<LA, LB>::stage, T>),
+                                   dim3(g),
                                    dim3(64), 0, st, tb);
             }, true);
             mats.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
