@@ -281,6 +281,10 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
         n[d] = hi[d] - lo[d] + 1;
         if (n[d] <= 0) return;
     }
+    /* sampled outputs: a pair image that cannot contribute is skipped before
+     * anything is tabulated */
+    if (c->nsamp > 0 && lv != c->samp_level) return;
+    if (c->mode == MODE_MAT && c->sp_slot && c->sp_slot[(long)p->sa * s->nshell + p->sb] < 0) return;
     const int la = p->la, lb = p->lb, na = ncart(la), nb = ncart(lb);
     const int ea = (c->mode == MODE_GRAD) ? la + 1 : la;
     const int eb = (c->mode == MODE_GRAD) ? lb + 1 : lb;

@@ -215,7 +215,7 @@ template <int NP, typename T>
 __device__ __forceinline__ void reduce_points(const T *acc, double (*red)[65], int p0, double &out)
 {
     constexpr int CH = NP < 32 ? NP : 32;   // points per LDS chunk
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int j = lane % CH, part = lane / CH;
 #pragma unroll
     for (int c0 = 0; c0 < NP; c0 += CH) {
@@ -289,6 +289,20 @@ struct RhoLane {
             __builtin_amdgcn_global_load_lds((const void *)(gd + 16 * k),
                                              (__attribute__((address_space(3))) void *)(lds + (8 + k) * 1024), 16, 0,
                                              0);
+    }
+    // pieces [k0, k1) only (two waves that share a batch each copy a part)
+    static __device__ __forceinline__ void stage_part(const RhoRec *__restrict__ rr, const T *__restrict__ Dpk,
+                                                      int lp, unsigned char *lds, int k0, int k1)
+    {
+        const unsigned char *gr = reinterpret_cast<const unsigned char *>(rr + lp);
+        const unsigned char *gd = reinterpret_cast<const unsigned char *>(Dpk + (long long)lp * dstride<T>(NA, NB));
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            if (k < k0 || k >= k1) continue;
+            const unsigned char *g = k < 8 ? gr + 16 * k : gd + 16 * (k - 8);
+            __builtin_amdgcn_global_load_lds((const void *)g, (__attribute__((address_space(3))) void *)(lds + k * 1024),
+                                             16, 0, 0);
+        }
     }
     // the same state straight from global memory (classes that do not stage)
     __device__ __forceinline__ void load_global(const RhoRec *__restrict__ rr, const T *__restrict__ Dpk, int lp)
@@ -453,17 +467,158 @@ k_rho(SegTable<RhoSeg> tab)
     }
 }
 
-// per class: points per pass (NPASS), waves per SIMD, and whether the next
-// batch is staged in LDS (chosen by measurement on the 256-water system)
-template <int LA, int LB> struct RhoSplit { static constexpr int npass = 1, wpe = 2; static constexpr bool stage = false; };
-template <> struct RhoSplit<1, 1> { static constexpr int npass = 1, wpe = 2; static constexpr bool stage = true; };
-template <> struct RhoSplit<2, 0> { static constexpr int npass = 1, wpe = 1; static constexpr bool stage = true; };
-template <> struct RhoSplit<2, 1> { static constexpr int npass = 1, wpe = 1; static constexpr bool stage = true; };
-template <> struct RhoSplit<2, 2> { static constexpr int npass = 2, wpe = 1; static constexpr bool stage = false; };
-template <> struct RhoSplit<3, 0> { static constexpr int npass = 1, wpe = 1; static constexpr bool stage = false; };
-template <> struct RhoSplit<3, 1> { static constexpr int npass = 2, wpe = 1; static constexpr bool stage = false; };
-template <> struct RhoSplit<3, 2> { static constexpr int npass = 2, wpe = 1; static constexpr bool stage = false; };
-template <> struct RhoSplit<3, 3> { static constexpr int npass = 4, wpe = 1; static constexpr bool stage = false; };
+// The same density for the heavy classes with two waves per block: both
+// waves walk the block's list with the same lane = pair image mapping and
+// share one copy of every batch in LDS (double-buffered, each wave copying
+// half of the pieces), and each wave accumulates 32 of the 64 points, which
+// halves the accumulator registers so that two such workgroups fit a SIMD.
+template <int LA, int LB, int WPE, typename T>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_rho2(SegTable<RhoSeg> tab)
+{
+    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
+    using Lane = RhoLane<T, NA, NB>;
+    constexpr int SB = Lane::STAGE;
+    constexpr int REDB = 2 * 32 * 65 * 8;
+    constexpr int LDSB = 2 * SB > REDB ? 2 * SB : REDB;
+    // two staging buffers, and after the last batch one reduction buffer per wave
+    __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const RhoSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
+    if (item >= sg.count) return;
+    const LevelGeom &G = sg.G;
+    const int2 *__restrict__ inc = sg.inc;
+    const T *__restrict__ Dpk = (const T *)sg.Dpk;
+    const int p0 = sg.p0;
+    const int b = sg.blk[item];   // block slot
+    int kx, ky, kz;
+    slot_block(G, b, kx, ky, kz);
+    const int kk[3] = {kx, ky, kz};
+    const long long s0 = sg.inc_off[b], s1 = sg.inc_off[b + 1];
+    const RhoRec *rr = sg.rr;
+    const int kh = (Lane::NCH + 1) / 2;                 // pieces copied by wave 0
+    const int k0 = w ? kh : 0, k1 = w ? Lane::NCH : kh;
+    T acc[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = T(0);
+    int2 en1 = inc[s0 + lane < s1 ? s0 + lane : s1 - 1];
+    int2 en2 = inc[s0 + 64 + lane < s1 ? s0 + 64 + lane : s1 - 1];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    Lane::stage_part(rr, Dpk, en1.x - p0, lds, k0, k1);
+    int buf = 0;
+    for (long long s = s0; s < s1; s += 64) {
+        const bool act = s + lane < s1;
+        const int2 en = en1;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's pieces of the batch
+        __syncthreads();                                    // and the other wave's; old buffer free
+        Lane cur;
+        cur.load(lds + buf * SB, lane);
+        if (s + 64 < s1) Lane::stage_part(rr, Dpk, en2.x - p0, lds + (buf ^ 1) * SB, k0, k1);
+        buf ^= 1;
+        en1 = en2;
+        {
+            const long long q2 = s + 128 + lane;
+            en2 = inc[q2 < s1 ? q2 : s1 - 1];
+        }
+        double fx[4], fy[4], fz[4];
+        const double x0 = (double)(4 * kk[0] + shift_of(en.y, 0) * G.N[0]) * G.h[0];
+        const double y0 = (double)(4 * kk[1] + shift_of(en.y, 1) * G.N[1]) * G.h[1];
+        const double z0 = (double)(4 * kk[2] + shift_of(en.y, 2) * G.N[2]) * G.h[2];
+        const double dP[3] = {x0 - cur.P[0], y0 - cur.P[1], z0 - cur.P[2]};
+        block_envelope(cur.ap, dP, G, cur.c, fx, fy, fz);
+        const T ER = (T)cur.ER;
+        const T on = act ? T(1) : T(0);
+        const double xa0 = x0 - cur.A[0], ya0 = y0 - cur.A[1], za0 = z0 - cur.A[2];
+        const T abx = (T)cur.AB[0], aby = (T)cur.AB[1], abz = (T)cur.AB[2];
+#pragma unroll
+        for (int ix = 0; ix < 2; ++ix) {
+            const int tx = 2 * w + ix;
+            const T xa = (T)(xa0 + tx * G.h[0]);
+            const T xb = xa + abx;
+            const T ex = (T)(w ? fx[2 + ix] : fx[ix]) * on;
+#pragma unroll
+            for (int ty = 0; ty < 4; ++ty) {
+                const T ya = (T)(ya0 + ty * G.h[1]);
+                const T yb = ya + aby;
+                const T exy = ex * (T)fy[ty];
+#pragma unroll
+                for (int tz = 0; tz < 4; ++tz) {
+                    const T za = (T)(za0 + tz * G.h[2]);
+                    const T zb = za + abz;
+                    T E = exy * (T)fz[tz];
+                    E = (E >= ER) ? E : T(0);
+                    T a[NA], bb[NB];
+                    monomials<LA, T>(xa, ya, za, a);
+                    monomials<LB, T>(xb, yb, zb, bb);
+                    T sum = T(0);
+#pragma unroll
+                    for (int i = 0; i < NA; ++i) {
+                        T t = T(0);
+#pragma unroll
+                        for (int jb = 0; jb < NB; ++jb) t += cur.Dk[i * NB + jb] * bb[jb];
+                        sum += a[i] * t;
+                    }
+                    acc[ix * 16 + ty * 4 + tz] += E * sum;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    __syncthreads();   // every read of the staging buffers is done
+    double mine = 0.0;
+    reduce_points<32, T>(acc, reinterpret_cast<double(*)[65]>(lds + w * (32 * 65 * 8)), 0, mine);
+    if (lane < 32) {
+        const int p = 32 * w + lane;
+        const int tx = p >> 4, ty = (p >> 2) & 3, tz = p & 3;
+        const int wx = 4 * kx + tx, wy = 4 * ky + ty, wz = 4 * kz + tz;
+        if (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) {
+            const long long o = ((long long)wx * G.N[1] + wy) * G.N[2] + wz;
+            sg.rho[o] += mine;
+        }
+    }
+}
+
+// per class: points per pass (NPASS), waves per SIMD, whether the next batch
+// is staged in LDS, and whether two waves share a block (k_rho2, at WPE2
+// workgroups per SIMD) (chosen by measurement on the 256-water system)
+template <int LA, int LB> struct RhoSplit {
+    static constexpr int npass = 1, wpe = 2, wpe2 = 1;
+    static constexpr bool stage = false, two = false;
+};
+template <> struct RhoSplit<1, 1> {
+    static constexpr int npass = 1, wpe = 2, wpe2 = 2;
+    static constexpr bool stage = true, two = false;
+};
+template <> struct RhoSplit<2, 0> {
+    static constexpr int npass = 1, wpe = 1, wpe2 = 2;
+    static constexpr bool stage = true, two = true;
+};
+template <> struct RhoSplit<2, 1> {
+    static constexpr int npass = 1, wpe = 1, wpe2 = 2;
+    static constexpr bool stage = true, two = false;
+};
+template <> struct RhoSplit<2, 2> {
+    static constexpr int npass = 2, wpe = 1, wpe2 = 2;
+    static constexpr bool stage = false, two = false;
+};
+template <> struct RhoSplit<3, 0> {
+    static constexpr int npass = 1, wpe = 1, wpe2 = 1;
+    static constexpr bool stage = false, two = false;
+};
+template <> struct RhoSplit<3, 1> {
+    static constexpr int npass = 2, wpe = 1, wpe2 = 1;
+    static constexpr bool stage = false, two = false;
+};
+template <> struct RhoSplit<3, 2> {
+    static constexpr int npass = 2, wpe = 1, wpe2 = 1;
+    static constexpr bool stage = false, two = false;
+};
+template <> struct RhoSplit<3, 3> {
+    static constexpr int npass = 4, wpe = 1, wpe2 = 1;
+    static constexpr bool stage = false, two = false;
+};
 
 // ----------------------------------------------- pair-major traversal (mat, grad)
 
@@ -985,11 +1140,13 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
             packs.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
                 hipLaunchKernelGGL((k_pack_density<T, NA, NB>), dim3(g), dim3(256), 0, st, tb);
             }, false);
+            using RS = RhoSplit<LA, LB>;
             rhos.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
-                hipLaunchKernelGGL((k_rho<LA, LB, RhoSplit<LA, LB>::npass, RhoSplit<LA, LB>::wpe,
-                                          RhoSplit<LA, LB>::stage, T>),
-                                   dim3(g),
-                                   dim3(64), 0, st, tb);
+                if constexpr (RS::two)
+                    hipLaunchKernelGGL((k_rho2<LA, LB, RS::wpe2, T>), dim3(g), dim3(128), 0, st, tb);
+                else
+                    hipLaunchKernelGGL((k_rho<LA, LB, RS::npass, RS::wpe, RS::stage, T>), dim3(g), dim3(64), 0, st,
+                                       tb);
             }, true);
             mats.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
                 hipLaunchKernelGGL((k_mat<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
