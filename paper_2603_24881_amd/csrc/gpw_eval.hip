@@ -129,13 +129,6 @@ __device__ __forceinline__ void poly_grad(T x, T y, T z, const T *t, T *g)
         }
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // --------------------------------------------------------- small kernels
 
 // out = (D + D^T) / 2 through 32x32 LDS tiles (both reads coalesced).
@@ -814,6 +807,35 @@ __device__ __forceinline__ void for_each_point(const PairRec &r, const T *te, co
     }
 }
 
+// Wave sums of the K per-lane accumulators of a pair-major kernel, eight at
+// a time through LDS (red[8][65], the kernel's LDS area once the traversal is
+// done): lane 8q + s adds eight values of accumulator q, three shuffles
+// finish the sum, and lane 8q applies emit(k, sum) for k = chunk + q.  The
+// eight results of a chunk leave in parallel instead of one lane issuing
+// every atomic.
+constexpr size_t kRedBytes = 8 * 65 * sizeof(double);
+template <int K, typename T, typename Emit>
+__device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit &&emit)
+{
+    const int lane = threadIdx.x;
+    const int q = lane >> 3, seg = lane & 7;
+#pragma unroll
+    for (int c0 = 0; c0 < K; c0 += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (c0 + u < K) red[u * 65 + lane] = (double)acc[c0 + u];
+        __syncthreads();
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v += red[q * 65 + seg * 8 + m];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        if (seg == 0 && c0 + q < K) emit(c0 + q, v);
+        __syncthreads();
+    }
+}
+
 // LDS layout of the pair-major kernels: te[3][wmax], td[3][wmax] (T), then the
 // block lists bl[3][emax], their counts and the block rows (at most emax^2).
 template <typename T>
@@ -833,7 +855,8 @@ struct PairSmem {
     {
         size_t off = sizeof(T) * 6 * (size_t)wmax;
         off = (off + 15) & ~size_t(15);
-        return off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)emax * emax;
+        const size_t b = off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)emax * emax;
+        return b > kRedBytes ? b : kRedBytes;   // the area is reused for the final reduction
     }
 };
 
@@ -875,16 +898,12 @@ k_mat(SegTable<PairSeg> tab)
         }
     });
     const double scale = 0.5 * G.w * r.Kw;
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const double v = wave_sum((double)acc[i * NB + j]);
-            if (threadIdx.x == 0) {
-                atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * v);
-                atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * v);
-            }
-        }
+    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+    wave_reduce_emit<NA * NB, T>(acc, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
+        const int i = k / NB, j = k - (k / NB) * NB;
+        atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * v);
+        atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * v);
+    });
 }
 
 template <int LA, int LB, typename T>
@@ -945,15 +964,11 @@ k_grad(SegTable<PairSeg> tab)
         gB[2] += two_ab * fS * zb - f * pb[2];
     });
     const double scale = G.w * r.Kw;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double va = wave_sum((double)gA[d]);
-        const double vb = wave_sum((double)gB[d]);
-        if (threadIdx.x == 0) {
-            atomicAdd(&sg.out[3 * r.atom_a + d], scale * va);
-            atomicAdd(&sg.out[3 * r.atom_b + d], scale * vb);
-        }
-    }
+    const T g6[6] = {gA[0], gA[1], gA[2], gB[0], gB[1], gB[2]};
+    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+    wave_reduce_emit<6, T>(g6, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
+        atomicAdd(&sg.out[3 * (k < 3 ? r.atom_a : r.atom_b) + (k < 3 ? k : k - 3)], scale * v);
+    });
 }
 
 // ------------------------------------------------------------ launchers
