@@ -668,6 +668,25 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             bl[d * emax + e] = eb;
         }
         if (threadIdx.x == 0) cnt[d] = n;
+        if (d == 2) {
+            // first z entry whose upper end reaches P: the gaps fall before it
+            // and rise from it on
+            int em = n;
+            for (int e0 = 0; e0 < n && em == n; e0 += 64) {
+                const int e = e0 + (int)threadIdx.x;
+                bool f = false;
+                if (e < n) {
+                    const int gi = g0 + e;
+                    const int S = floordiv(gi, nb);
+                    const int k = gi - S * nb;
+                    const int u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
+                    f = (double)u1 * G.h[2] >= r.P[2];
+                }
+                const unsigned long long m = __ballot(f);
+                if (m) em = e0 + __ffsll((long long)m) - 1;
+            }
+            if (threadIdx.x == 0) cnt[3] = em;
+        }
     }
 }
 
@@ -704,7 +723,7 @@ __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, 
                                           const int *cnt, BlockRow *rows)
 {
     const int lane = threadIdx.x;
-    const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]);
+    const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]), em = uni(cnt[3]);
     const AxisBlock *blx = bl, *bly = bl + emax, *blz = bl + 2 * emax;
     int nrows = 0;
     for (int base = 0; base < nx * ny; base += 64) {
@@ -716,9 +735,26 @@ __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, 
             const double g = blx[ex].gap2 + bly[ey].gap2;
             if (g <= R2c) {
                 const double rem = R2c - g;
-                int zlo = 0, zhi = nz - 1;
-                while (zlo < nz && blz[zlo].gap2 > rem) ++zlo;
-                while (zhi >= zlo && blz[zhi].gap2 > rem) --zhi;
+                // the z gaps fall on [0, em) and rise on [em, nz): the run of
+                // entries with gap <= rem from two binary searches
+                int zlo, zhi;
+                {
+                    int a = 0, b = em;   // first e < em with gap <= rem, else em
+                    while (a < b) {
+                        const int c = (a + b) >> 1;
+                        if (blz[c].gap2 <= rem) b = c; else a = c + 1;
+                    }
+                    zlo = a;
+                }
+                {
+                    int a = em - 1, b = nz - 1;   // last e >= em with gap <= rem, else em - 1
+                    while (a < b) {
+                        const int c = (a + b + 1) >> 1;
+                        if (blz[c].gap2 <= rem) a = c; else b = c - 1;
+                    }
+                    zhi = a;
+                }
+                if (zlo == em && (em >= nz || blz[em].gap2 > rem)) zlo = nz;   // nothing on [em, nz)
                 ok = zlo <= zhi;
                 row.bxy = (blx[ex].k * G.nb[1] + bly[ey].k) * G.nb[2];
                 row.jx0 = blx[ex].j0;
