@@ -83,3 +83,57 @@ def test_batch_empty_and_repeated_plan():
     assert np.array_equal(to_np(r1[0]), to_np(g.rho(D1)[0]))
     assert np.array_equal(to_np(r2[0]), to_np(g.rho(D2)[0]))
     g.close()
+
+
+def test_batch_with_more_segments_than_one_launch_holds():
+    """Six plans of four levels each: 24 (task, level) segments per class, more
+    than one launch's table holds, so the launches are split; every task still
+    equals its single call."""
+    import torch
+    from paper_2603_24881_amd.gpw import GPW
+    systems = [synth.config5(8, 0), synth.config5(8, 1), synth.config5(16, 0), synth.config5(16, 1),
+               synth.config2(), synth.config5(32, 0)]
+    plans = [GPW(s) for s in systems]
+    assert all(len(g.meshes) == 4 for g in plans)
+    Ds = [to_dev(synth.make_density(s)) for s in systems]
+    Vs = [[to_dev(v) for v in synth.make_potentials(g.meshes, s.seed)] for g, s in zip(plans, systems)]
+    ref = [([to_np(r) for r in g.rho(D)], to_np(g.mat(V))) for g, D, V in zip(plans, Ds, Vs)]
+    outs, tasks = [], []
+    for g, D, V in zip(plans, Ds, Vs):
+        rho = g.new_grids()
+        M = torch.empty((g.n_ao, g.n_ao), dtype=torch.float64, device=D.device)
+        outs.append((rho, M))
+        tasks += [dict(plan=g.plan, op=_lib.GPW_OP_RHO, D=D, rho=rho), dict(plan=g.plan, op=_lib.GPW_OP_MAT, v=V, out=M)]
+    _lib.gpw_eval_batch(tasks)
+    torch.cuda.synchronize()
+    for (rho_r, M_r), (rho, M) in zip(ref, outs):
+        for a, b in zip(rho, rho_r):
+            assert np.array_equal(to_np(a), b)
+        assert rel_err(to_np(M), M_r) < 1e-12
+    for g in plans:
+        g.close()
+
+
+def test_one_plan_on_two_streams():
+    """One plan evaluated concurrently on two streams with distinct outputs."""
+    import torch
+    from paper_2603_24881_amd.gpw import GPW
+    s = synth.config2()
+    g = GPW(s)
+    D1 = to_dev(synth.make_density(s))
+    D2 = to_dev(synth.make_density(s, seed=s.seed + 1))
+    ref1 = [to_np(r) for r in g.rho(D1)]
+    ref2 = [to_np(r) for r in g.rho(D2)]
+    torch.cuda.synchronize()
+    st1, st2 = torch.cuda.Stream(), torch.cuda.Stream()
+    r1, r2 = g.new_grids(), g.new_grids()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        g.rho(D1, out=r1, stream=st1)
+        g.rho(D2, out=r2, stream=st2)
+    torch.cuda.synchronize()
+    for a, b in zip(r1, ref1):
+        assert np.array_equal(to_np(a), b)
+    for a, b in zip(r2, ref2):
+        assert np.array_equal(to_np(a), b)
+    g.close()
