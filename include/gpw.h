@@ -141,7 +141,9 @@ typedef struct {
  * (Sec. III.B; appendix on GTO screening, Algs. 4 and 5).  All host inputs
  * are copied; the caller may free them on return.  The plan owns its device
  * memory on cut->device.  Synchronous.  Errors: GPW_EINVAL for NULL or invalid
- * arguments, GPW_EUNSUPPORTED for a non-diagonal cell or l > 3, GPW_ENOMEM,
+ * arguments, GPW_EUNSUPPORTED for a non-diagonal cell, l > 3, or a truncation
+ * sphere too wide for the kernels (more than 1024 points per axis, more than
+ * 127 cell periods, or point tables beyond one workgroup's LDS), GPW_ENOMEM,
  * GPW_EDEVICE. */
 gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis,
                     const gpw_cutoffs *cut, gpw_plan_t *out);

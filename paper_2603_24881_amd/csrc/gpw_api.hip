@@ -231,6 +231,23 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
                                                                : GPW_EDEVICE;
         return fail(st_code, "gpw_plan: " + err);
     }
+    {
+        // the pair-major kernels keep a pair image's point tables, block lists
+        // and block rows in LDS: the widest sphere must fit one workgroup's share
+        int lds_max = 0;
+        (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
+        const size_t need = gpw::pair_kernel_lds_bytes(pl->info.max_box_width + 8,
+                                                       pl->max_axis_blocks > 0 ? pl->max_axis_blocks : 1,
+                                                       pl->precision);
+        if (lds_max > 0 && need > (size_t)lds_max) {
+            const std::string msg = "gpw_plan: the widest truncation sphere (" +
+                                    std::to_string(pl->info.max_box_width) + " points per axis) needs " +
+                                    std::to_string(need) + " bytes of LDS per workgroup, above the device's " +
+                                    std::to_string(lds_max);
+            free_plan(pl);
+            return fail(GPW_EUNSUPPORTED, msg);
+        }
+    }
     gpw_plan_info &I = pl->info;
     I.nlevels = pl->nlevels;
     for (int l = 0; l < pl->nlevels; ++l) {

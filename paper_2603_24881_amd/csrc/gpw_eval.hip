@@ -1212,6 +1212,11 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
     return e;
 }
 
+size_t pair_kernel_lds_bytes(int wmax, int emax, int precision)
+{
+    return precision == GPW_FP32 ? PairSmem<float>::bytes(wmax, emax) : PairSmem<double>::bytes(wmax, emax);
+}
+
 hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st)
 {
     std::vector<TaskRef> t64, t32;

@@ -103,3 +103,20 @@ def test_everything_screened_out_gives_zeros():
     torch.cuda.synchronize()
     assert float(rho[0].abs().max()) == 0.0 and float(M.abs().max()) == 0.0 and float(G.abs().max()) == 0.0
     g.close()
+
+
+def test_too_wide_sphere_is_rejected_with_a_message():
+    """A very diffuse function on a very fine single mesh: its truncation
+    sphere's point tables would not fit a workgroup's LDS; the plan call fails
+    with GPW_EUNSUPPORTED and says why instead of failing at launch."""
+    from paper_2603_24881_amd import _lib
+    from paper_2603_24881_amd.gpw import GPW
+    s = synth.System(name="wide", cell=np.array([40.0, 40.0, 40.0]), coords=np.array([[20.0, 20.0, 20.0]]),
+                     shell_atom=np.array([0], dtype=np.int32), shell_l=np.array([0], dtype=np.int32),
+                     shell_nprim=np.array([1], dtype=np.int32), shell_prim0=np.array([0], dtype=np.int32),
+                     exps=np.array([0.02]), coefs=np.array([1.0]), ke_cutoff_ry=[],
+                     mesh=np.array([[600, 600, 600]], dtype=np.int32), tau=1e-6, n_occ=1)
+    with pytest.raises(_lib.GPWError) as ei:
+        GPW(s)
+    log(f"  {ei.value}")
+    assert ei.value.status == 2 and "LDS" in str(ei.value)   # GPW_EUNSUPPORTED
