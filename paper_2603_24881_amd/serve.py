@@ -11,11 +11,14 @@ carries the collocation task of every request admitted since the last round
 and the integration (or gradient) task of every request that finished its
 collocation in the previous round, so requests of different systems and
 sizes share the same launches; after the batch the Poisson step of the new
-requests runs.  A request therefore completes in two rounds.  Requests that
+requests runs.  A request therefore completes in two rounds, or in one when
+no other request is waiting as the round starts (then the new requests' second
+stage follows in the same round and there is nothing to batch it with anyway).
+Requests that
 arrive while a round is on the device are admitted at the start of the next
-round, in arrival order, as long as the number of active requests stays
-below ``max_active`` and their device memory (plus that of their plan, when
-it is not resident) fits the HBM budget; idle plans are evicted least
+round, in arrival order, as long as the number of requests starting their
+first stage in the round stays within ``max_active`` and their device memory
+(plus that of their plan, when it is not resident) fits the HBM budget; idle plans are evicted least
 recently used first to make room.  A request that can never fit is
 rejected.
 
@@ -120,7 +123,10 @@ class Scheduler:
         self.users[r.system] -= 1
 
     def _admit(self, pending, active, now):
-        while pending and pending[0].arrival <= now and len(active) < self.max_active:
+        # at the start of a round every active request is in its second stage
+        # and leaves with this round: the slots limit the new (first-stage) ones
+        new = sum(1 for r in active if r.stage == 0)
+        while pending and pending[0].arrival <= now and new < self.max_active:
             r = pending[0]
             if not self._fits_ever(r):
                 pending.popleft()
@@ -133,6 +139,7 @@ class Scheduler:
             r.stage = 0
             self.ex.begin(r)
             active.append(r)
+            new += 1
 
     # ---------------------------------------------------------- runs
     def run(self, requests):
@@ -148,16 +155,19 @@ class Scheduler:
                 continue
             s0 = [r for r in active if r.stage == 0]
             s1 = [r for r in active if r.stage == 1]
-            self.ex.round(s0, s1)
+            # nobody waiting: the new requests finish in this round too
+            fuse = not (pending and pending[0].arrival <= self.ex.now() - t0)
+            self.ex.round(s0, s1, fuse)
             now = self.ex.now() - t0
             self.rounds.append((len(s0), len(s1)))
-            for r in s1:
+            for r in s1 + (s0 if fuse else []):
                 r.done = now
                 self.ex.end(r)
                 self._release(r)
                 active.remove(r)
-            for r in s0:
-                r.stage = 1
+            if not fuse:
+                for r in s0:
+                    r.stage = 1
         return requests
 
     def run_sequential(self, requests):
@@ -283,22 +293,25 @@ class GPUExecutor:
         r.state["out"] = torch.empty(shape, dtype=torch.float64, device=self.dev)
         return r.state["out"]
 
-    def round(self, s0, s1):
+    def _second_stage(self, r):
         from . import _lib
-        tasks = []
-        for r in s1:
-            g, _ = self.plans[r.system]
-            out = self._output(r)
-            if r.kind == FOCK:
-                tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_MAT, v=r.state["v"], out=out))
-            else:
-                tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_GRAD, D=r.state["D"], v=r.state["v"], out=out))
+        g, _ = self.plans[r.system]
+        out = self._output(r)
+        if r.kind == FOCK:
+            return dict(plan=g.plan, op=_lib.GPW_OP_MAT, v=r.state["v"], out=out)
+        return dict(plan=g.plan, op=_lib.GPW_OP_GRAD, D=r.state["D"], v=r.state["v"], out=out)
+
+    def round(self, s0, s1, finish_new=False):
+        from . import _lib
+        tasks = [self._second_stage(r) for r in s1]
         for r in s0:
             g, _ = self.plans[r.system]
             tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_RHO, D=r.state["D"], rho=r.state["rho"]))
         _lib.gpw_eval_batch(tasks)
         for r in s0:
             self._finish_poisson(r)
+        if finish_new and s0:
+            _lib.gpw_eval_batch([self._second_stage(r) for r in s0])
         self.torch.cuda.synchronize(self.dev)
 
     def single(self, r):

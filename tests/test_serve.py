@@ -53,10 +53,10 @@ class FakeExecutor:
         self._check_budget()
         self.log.append(("begin", r.rid))
 
-    def round(self, s0, s1):
+    def round(self, s0, s1, finish_new=False):
         assert all(r.stage == 0 for r in s0) and all(r.stage == 1 for r in s1)
-        self.log.append(("round", [r.rid for r in s0], [r.rid for r in s1]))
-        self.t += 1e-3 * (1 + len(s0) + len(s1))
+        self.log.append(("round", [r.rid for r in s0], [r.rid for r in s1], finish_new))
+        self.t += 1e-3 * (1 + len(s0) * (2 if finish_new else 1) + len(s1))
 
     def single(self, r):
         self.log.append(("single", r.rid))
@@ -80,28 +80,45 @@ def _sched(ex, budget, max_active=16):
     return s
 
 
-def test_every_request_completes_in_two_rounds():
+def test_every_request_completes_in_one_or_two_rounds():
+    """Two rounds (first stage, then second stage), or one when nobody was
+    waiting as its first round started."""
     ex = FakeExecutor({"a": 10, "b": 20}, {"a": 1, "b": 2})
-    s = _sched(ex, 1000)
+    s = _sched(ex, 1000, max_active=3)
     reqs = [Request(i, FOCK if i % 2 else GRAD, "ab"[i % 2], 0.0005 * i) for i in range(20)]
     s.run(reqs)
+    fused = 0
     for r in reqs:
         assert r.error is None and r.done >= r.admitted >= r.arrival
         rounds = [e for e in ex.log if e[0] == "round" and (r.rid in e[1] or r.rid in e[2])]
-        assert len(rounds) == 2 and r.rid in rounds[0][1] and r.rid in rounds[1][2]
+        assert r.rid in rounds[0][1]
+        if rounds[0][3]:
+            assert len(rounds) == 1
+            fused += 1
+        else:
+            assert len(rounds) == 2 and r.rid in rounds[1][2]
+    assert 0 < fused < len(reqs)
 
 
-def test_arrivals_during_a_round_join_the_next_round():
+def test_lone_request_finishes_in_one_round():
     ex = FakeExecutor({"a": 10}, {"a": 1})
     s = _sched(ex, 1000)
-    r0 = Request(0, FOCK, "a", 0.0)
-    r1 = Request(1, GRAD, "a", 0.0015)      # arrives while round 1 (2 ms) runs
-    s.run([r0, r1])
+    r = Request(0, FOCK, "a", 0.0)
+    s.run([r])
+    assert [e for e in ex.log if e[0] == "round"] == [("round", [0], [], True)]
+    assert r.done == pytest.approx(0.003)
+
+
+def test_waiting_requests_join_the_next_round():
+    """Under load the new requests' first stage shares the launches of the
+    previous ones' second stage."""
+    ex = FakeExecutor({"a": 10}, {"a": 1})
+    s = _sched(ex, 1000, max_active=2)
+    reqs = [Request(i, FOCK if i % 2 else GRAD, "a", 0.0) for i in range(5)]
+    s.run(reqs)
     rounds = [e for e in ex.log if e[0] == "round"]
-    assert rounds[0] == ("round", [0], [])
-    assert rounds[1] == ("round", [1], [0])    # r1's collocation shares r0's integration launch
-    assert rounds[2] == ("round", [], [1])
-    assert r1.admitted == pytest.approx(0.002)
+    assert rounds == [("round", [0, 1], [], False), ("round", [2, 3], [0, 1], False),
+                      ("round", [4], [2, 3], True)]
 
 
 def test_admission_in_arrival_order_under_budget():
@@ -145,7 +162,7 @@ def test_max_active_is_respected():
     s.run(reqs)
     for e in ex.log:
         if e[0] == "round":
-            assert len(e[1]) + len(e[2]) <= 3
+            assert len(e[1]) <= 3 and len(e[2]) <= 3
 
 
 def test_sequential_baseline_and_summary():
