@@ -236,8 +236,7 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
         // and block rows in LDS: the widest sphere must fit one workgroup's share
         int lds_max = 0;
         (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
-        const size_t need = gpw::pair_kernel_lds_bytes(pl->info.max_box_width + 8,
-                                                       pl->max_axis_blocks > 0 ? pl->max_axis_blocks : 1,
+        const size_t need = gpw::pair_kernel_lds_bytes(pl->max_axis_blocks > 0 ? pl->max_axis_blocks : 1,
                                                        pl->precision);
         if (lds_max > 0 && need > (size_t)lds_max) {
             const std::string msg = "gpw_plan: the widest truncation sphere (" +

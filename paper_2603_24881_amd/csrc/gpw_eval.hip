@@ -52,7 +52,7 @@ __device__ __forceinline__ int seg_of(const SegTable<S> &t, long long item)
 
 // element-wise segments, one 256-thread block per item
 struct FillSeg { long long item0; double *p; long long count; };
-struct GridSeg { long long item0; const double *v; double *vb; long long count; LevelGeom G; };
+struct GridSeg { long long item0; const double *v; double *vb; long long count; int vz; LevelGeom G; };
 struct SymSeg { long long item0; const double *D; void *out; int n, nt; };
 struct PackSeg { long long item0; const PairRec *pairs; const double *D; void *out; long long count; int n; };
 // one wave per grid block (rho) or per pair image (mat, grad)
@@ -72,14 +72,17 @@ struct RhoSeg {
     int p0;                      // plan index of the group's first pair image
     LevelGeom G;
 };
+// Blocks of slack past the end of a block copy: the pair-major traversal
+// always loads four whole blocks from a run's start.
+constexpr int kBlockCopyTail = 4;
 struct PairSeg {
     long long item0;
     long long count;             // pair images
     const PairRec *pairs;        // records of the (level, class) group
     const void *Dm;              // grad: symmetrised D
-    const double *Vb;            // block-ordered level potential
+    const double *Vb;            // block-ordered level potential, vz blocks per (x, y) column
     double *out;                 // mat: M; grad: natm x 3
-    int n_ao, wmax, emax;
+    int n_ao, emax, vz;
     LevelGeom G;
 };
 
@@ -616,10 +619,10 @@ template <> struct RhoSplit<3, 3> {
 // ----------------------------------------------- pair-major traversal (mat, grad)
 
 // Per-axis list entry of the blocks a pair image's bounding box meets:
-// wrapped block index k, offset of the block's first point in the 1-D tables,
-// squared distance from P to the block's extent along the axis.
+// wrapped block index k and the squared distance from P to the block's
+// extent along the axis.
 struct AxisBlock {
-    int k, j0;
+    int k, pad;
     double gap2;
 };
 
@@ -632,24 +635,21 @@ __device__ __forceinline__ double uni(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// LDS set-up of one pair image: 1-D tables over u in [lo-3, hi+3] per axis
-// (envelope exp(-alpha_p (x_u - P)^2) and offset x_u - A) and the per-axis
-// lists of the blocks (with fold shifts) its bounding box meets, one entry per
-// lane.  emax bounds every list (the plan's longest).
+// 1-D point tables of a pair image, at point 4 e + t of an axis (point t of
+// block list entry e): the envelope factor exp(-alpha_p (x - P)^2) and the
+// offsets x - A (and, along z, x - B).
+template <typename T> struct alignas(2 * sizeof(T)) PtXY { T e, a; };
+template <typename T> struct alignas(4 * sizeof(T)) PtZ { T e, a, b, pad; };
+
+// LDS set-up of one pair image: per axis, the list of the blocks (with fold
+// shifts) its bounding box meets, one entry per lane, and the point tables of
+// the entries, so that the points of a run of consecutive entries sit at
+// consecutive table positions.  emax bounds every list (the plan's longest).
 template <typename T>
-__device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G, T *te, T *td, int wmax,
+__device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G, PtXY<T> *txy, PtZ<T> *tz,
                                            AxisBlock *bl, int emax, int *cnt)
 {
     const double ap = r.aa + r.ab;
-    for (int d = 0; d < 3; ++d) {
-        const int W = r.hi[d] - r.lo[d] + 7;
-        for (int i = threadIdx.x; i < W; i += 64) {
-            const double x = (double)(r.lo[d] - 3 + i) * G.h[d];
-            const double dx = x - r.P[d];
-            te[d * wmax + i] = (T)exp(-ap * dx * dx);
-            td[d * wmax + i] = (T)(x - r.A[d]);
-        }
-    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int N = G.N[d], nb = G.nb[d];
@@ -663,9 +663,24 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             const int u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
             AxisBlock eb;
             eb.k = k;
-            eb.j0 = u0 - (r.lo[d] - 3);
+            eb.pad = 0;
             eb.gap2 = axis_gap2(r.P[d], (double)u0 * G.h[d], (double)u1 * G.h[d]);
             bl[d * emax + e] = eb;
+        }
+        // points of the entries; a partial block's padding points get the
+        // coordinates past the period's end (their potential is zero)
+        for (int i = threadIdx.x; i < 4 * n; i += 64) {
+            const int gi = g0 + (i >> 2);
+            const int S = floordiv(gi, nb);
+            const int u = 4 * (gi - S * nb) + (i & 3) + S * N;
+            const double x = (double)u * G.h[d];
+            const double dx = x - r.P[d];
+            const double e = exp(-ap * dx * dx), a = x - r.A[d];
+            if (d < 2) {
+                txy[d * 4 * emax + i] = PtXY<T>{(T)e, (T)a};
+            } else {
+                tz[i] = PtZ<T>{(T)e, (T)a, (T)(a + r.AB[2]), T(0)};
+            }
         }
         if (threadIdx.x == 0) cnt[d] = n;
         if (d == 2) {
@@ -690,9 +705,12 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
     }
 }
 
-// Copy of a level grid in 4x4x4-block order (block b = (kx nb1 + ky) nb2 + kz,
+// Copy of a level grid in 4x4x4-block order (block b = (kx nb1 + ky) vz + kz,
 // then the 64 points with the z index fastest), zero at the padding points
 // of partial blocks, so that one wave reads a block with one coalesced load.
+// Each (x, y) column holds vz >= nb2 blocks: past its nb2 blocks it repeats
+// the column periodically, so that a run of up to vz - nb2 + 1 blocks along z
+// that starts in the cell is contiguous in memory.
 __global__ void __launch_bounds__(256) k_block_grid(SegTable<GridSeg> tab)
 {
     const GridSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
@@ -703,24 +721,27 @@ __global__ void __launch_bounds__(256) k_block_grid(SegTable<GridSeg> tab)
     double *__restrict__ vb = sg.vb;
     const long long b = i >> 6;
     const int t = (int)(i & 63);
-    const int kz = (int)(b % G.nb[2]);
-    const int ky = (int)((b / G.nb[2]) % G.nb[1]);
-    const int kx = (int)(b / ((long long)G.nb[2] * G.nb[1]));
+    const int kz = (int)(b % sg.vz) % G.nb[2];
+    const int ky = (int)((b / sg.vz) % G.nb[1]);
+    const int kx = (int)(b / ((long long)sg.vz * G.nb[1]));
     const int wx = 4 * kx + (t >> 4), wy = 4 * ky + ((t >> 2) & 3), wz = 4 * kz + (t & 3);
     vb[i] = (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) ? v[((long long)wx * G.N[1] + wy) * G.N[2] + wz] : 0.0;
 }
 
 // One (x, y) row of blocks of a pair image whose z run meets the sphere:
-// the block-grid offset of its (x, y) block column, the LDS table offsets of
-// its x and y blocks, and the run [zlo, zhi] in the z block list.
+// the block-copy index of the run's first block (the run is contiguous
+// there), the x and y entries, and the run's first z entry and length.
 struct BlockRow {
-    int bxy, jx0, jy0, zz;   // zz = zlo | zhi << 16
+    int vb;    // block index in the level's block copy
+    int ex;    // x entry
+    int ey;    // y entry
+    int zn;    // zlo | n << 16
 };
 
 // Rows of the pair image's blocks, in (x block, y block) order: built by the
 // wave with one candidate row per lane and a ballot compaction.
-__device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, const AxisBlock *bl, int emax,
-                                          const int *cnt, BlockRow *rows)
+__device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, int vz, const AxisBlock *bl,
+                                          int emax, const int *cnt, BlockRow *rows)
 {
     const int lane = threadIdx.x;
     const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]), em = uni(cnt[3]);
@@ -756,10 +777,12 @@ __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, 
                 }
                 if (zlo == em && (em >= nz || blz[em].gap2 > rem)) zlo = nz;   // nothing on [em, nz)
                 ok = zlo <= zhi;
-                row.bxy = (blx[ex].k * G.nb[1] + bly[ey].k) * G.nb[2];
-                row.jx0 = blx[ex].j0;
-                row.jy0 = bly[ey].j0;
-                row.zz = zlo | (zhi << 16);
+                if (ok) {
+                    row.vb = (blx[ex].k * G.nb[1] + bly[ey].k) * vz + blz[zlo].k;
+                    row.ex = ex;
+                    row.ey = ey;
+                    row.zn = zlo | ((zhi - zlo + 1) << 16);
+                }
             }
         }
         const unsigned long long m = __ballot(ok);
@@ -772,74 +795,86 @@ __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, 
 // Visit every (block, shift) incidence of the pair image whose block meets
 // the truncation sphere (the incidences the partitioner lists), lane = point
 // of the block, row by row in (x, y, z) block order.  Blocks are taken four
-// at a time along a row's z run; the potential loads of the next four are
-// issued before the current four are used, so that their latency overlaps
-// the arithmetic.  body(f, xa, ya, za): f = v(r) exp(-alpha_p |r-P|^2) inside
-// the sphere, else 0; (xa, ya, za) = r - A.
+// at a time along a row's z run, which is contiguous both in the block copy
+// and in the z table.  The potential of the next four blocks is loaded
+// before the current four are used, so that the load latency overlaps the
+// arithmetic; the loads always cover four whole blocks (the block copy has
+// kBlockCopyTail blocks of slack at its end), which keeps their number fixed.
+// body(f, xa, ya, za, xb, yb, zb): f = v(r) exp(-alpha_p |r-P|^2) inside the
+// sphere, else 0; (xa, ya, za) = r - A, (xb, yb, zb) = r - B.
 template <typename T, typename Body>
-__device__ __forceinline__ void for_each_point(const PairRec &r, const T *te, const T *td, int wmax,
-                                               const AxisBlock *bl, int emax, const BlockRow *rows, int nrows,
-                                               const double *__restrict__ Vb, Body &&body)
+__device__ __forceinline__ void for_each_point(const PairRec &r, const PtXY<T> *txy, const PtZ<T> *tzt, int emax,
+                                               const BlockRow *rows, int nrows, const double *__restrict__ Vb,
+                                               Body &&body)
 {
     const int lane = threadIdx.x;
-    const int tx = lane >> 4, ty = (lane >> 2) & 3, tz = lane & 3;
+    const int E4 = 4 * emax;
     const T ER = (T)r.ER;
-    const AxisBlock *blz = bl + 2 * emax;
+    const T abx = (T)r.AB[0], aby = (T)r.AB[1];
+    const PtXY<T> *px = txy + (lane >> 4), *py = txy + E4 + ((lane >> 2) & 3);
+    const PtZ<T> *pz = tzt + (lane & 3);
     if (nrows <= 0) return;
-    // cursor: row index rr, first z entry ez of the batch
-    int rr = 0;
-    BlockRow row = rows[0];
-    int zhi = uni(row.zz) >> 16;
-    int ez = uni(row.zz) & 0xffff;
-    double vv[4];
-    int jz[4];
+    // batch cursor: row rr, its fields, offset i0 of the batch in the run
+    struct Cur {
+        int rr, i0, vb, ex, ey, zn;
+    };
+    auto fetch_row = [&](Cur &c) {
+        const BlockRow w = rows[c.rr];
+        c.vb = uni(w.vb);
+        c.ex = uni(w.ex);
+        c.ey = uni(w.ey);
+        c.zn = uni(w.zn);
+    };
+    auto load4 = [&](const Cur &c, double *v) {
+        const double *p = Vb + (long long)(c.vb + c.i0) * 64 + lane;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int e = ez + u <= zhi ? ez + u : zhi;
-        const double *vb = Vb + ((long long)uni(row.bxy) + uni(blz[e].k)) * 64;   // uniform
-        vv[u] = vb[lane];
-    }
-    for (;;) {
-        // next batch: the rest of this row's run, else the next row
-        int nrr = rr, nez = ez + 4, nzhi = zhi;
-        BlockRow nrow = row;
-        if (nez > zhi) {
-            nrr = rr + 1;
-            if (nrr < nrows) {
-                nrow = rows[nrr];
-                nez = uni(nrow.zz) & 0xffff;
-                nzhi = uni(nrow.zz) >> 16;
-            }
+        for (int u = 0; u < 4; ++u) v[u] = p[u * 64];
+    };
+    // advance c to the next batch; false at the end (c then stays put)
+    auto advance = [&](Cur &c) {
+        if (c.i0 + 4 < (c.zn >> 16)) {
+            c.i0 += 4;
+            return true;
         }
-        const bool more = nrr < nrows;
-        double vn[4];
-        if (more) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = nez + u <= nzhi ? nez + u : nzhi;
-                const double *vb = Vb + ((long long)uni(nrow.bxy) + uni(blz[e].k)) * 64;
-                vn[u] = vb[lane];
-            }
-        }
-        const int jx = row.jx0 + tx, jy = row.jy0 + ty;
-        const T xa = td[jx], ya = td[wmax + jy];
-        const T exy = te[jx] * te[wmax + jy];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) jz[u] = blz[ez + u <= zhi ? ez + u : zhi].j0 + tz;
+        if (c.rr + 1 >= nrows) return false;
+        c.rr += 1;
+        c.i0 = 0;
+        fetch_row(c);
+        return true;
+    };
+    auto run = [&](const Cur &c, const double *v) {
+        const PtXY<T> X = px[4 * c.ex], Y = py[4 * c.ey];
+        const T xb = X.a + abx, yb = Y.a + aby;
+        const T exy = X.e * Y.e;
+        const PtZ<T> *z = pz + 4 * ((c.zn & 0xffff) + c.i0);
+        const int m = (c.zn >> 16) - c.i0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (ez + u <= zhi) {
-                const T E = exy * te[2 * wmax + jz[u]];
-                body((E >= ER) ? (T)vv[u] * E : T(0), xa, ya, td[2 * wmax + jz[u]]);
+            if (u < m) {
+                const PtZ<T> Z = z[4 * u];
+                const T E = exy * Z.e;
+                body((E >= ER) ? (T)v[u] * E : T(0), X.a, Y.a, Z.a, xb, yb, Z.b);
             }
         }
-        if (!more) break;
-        rr = nrr;
-        row = nrow;
-        ez = nez;
-        zhi = nzhi;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) vv[u] = vn[u];
+    };
+    Cur a;
+    a.rr = 0;
+    a.i0 = 0;
+    fetch_row(a);
+    double va[4], vb4[4];
+    load4(a, va);
+    // two batches per trip, alternating the two potential buffers
+    for (;;) {
+        Cur b = a;
+        const bool mb = advance(b);
+        load4(b, vb4);
+        run(a, va);
+        if (!mb) break;
+        a = b;
+        const bool ma = advance(a);
+        load4(a, va);
+        run(b, vb4);
+        if (!ma) break;
     }
 }
 
@@ -872,25 +907,28 @@ __device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit
     }
 }
 
-// LDS layout of the pair-major kernels: te[3][wmax], td[3][wmax] (T), then the
-// block lists bl[3][emax], their counts and the block rows (at most emax^2).
+// LDS layout of the pair-major kernels: the x and y point tables
+// txy[2][4 emax], the z point table tz[4 emax], then the block lists
+// bl[3][emax], their counts and the block rows (at most emax^2).
 template <typename T>
 struct PairSmem {
-    static __device__ __forceinline__ void carve(unsigned char *raw, int wmax, int emax, T *&te, T *&td,
+    static __host__ __device__ size_t table_bytes(int emax)
+    {
+        const size_t b = (2 * sizeof(PtXY<T>) + sizeof(PtZ<T>)) * 4 * (size_t)emax;
+        return (b + 15) & ~size_t(15);
+    }
+    static __device__ __forceinline__ void carve(unsigned char *raw, int emax, PtXY<T> *&txy, PtZ<T> *&tz,
                                                  AxisBlock *&bl, int *&cnt, BlockRow *&rows)
     {
-        te = reinterpret_cast<T *>(raw);
-        td = te + 3 * wmax;
-        size_t off = sizeof(T) * 6 * (size_t)wmax;
-        off = (off + 15) & ~size_t(15);
-        bl = reinterpret_cast<AxisBlock *>(raw + off);
+        tz = reinterpret_cast<PtZ<T> *>(raw);
+        txy = reinterpret_cast<PtXY<T> *>(tz + 4 * emax);
+        bl = reinterpret_cast<AxisBlock *>(raw + table_bytes(emax));
         cnt = reinterpret_cast<int *>(bl + 3 * emax);
         rows = reinterpret_cast<BlockRow *>(cnt + 4);
     }
-    static size_t bytes(int wmax, int emax)
+    static size_t bytes(int emax)
     {
-        size_t off = sizeof(T) * 6 * (size_t)wmax;
-        off = (off + 15) & ~size_t(15);
+        const size_t off = table_bytes(emax);
         const size_t b = off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)emax * emax;
         return b > kRedBytes ? b : kRedBytes;   // the area is reused for the final reduction
     }
@@ -902,7 +940,8 @@ k_mat(SegTable<PairSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
-    T *te, *td;
+    PtXY<T> *txy;
+    PtZ<T> *tz;
     AxisBlock *bl;
     int *cnt;
     BlockRow *rows;
@@ -910,22 +949,21 @@ k_mat(SegTable<PairSeg> tab)
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const LevelGeom &G = sg.G;
-    const int wmax = sg.wmax, n_ao = sg.n_ao, emax = sg.emax;
+    const int n_ao = sg.n_ao, emax = sg.emax;
     const double *__restrict__ Vb = sg.Vb;
-    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt, rows);
+    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
-    pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
+    pair_setup<T>(r, G, txy, tz, bl, emax, cnt);
     __syncthreads();
-    const int nrows = build_rows(r.R2 * kCullSlack, G, bl, emax, cnt, rows);
+    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
     __syncthreads();
     T acc[NA * NB];
 #pragma unroll
     for (int i = 0; i < NA * NB; ++i) acc[i] = T(0);
-    const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
-    for_each_point<T>(r, te, td, wmax, bl, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za) {
+    for_each_point<T>(r, txy, tz, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za, T xb, T yb, T zb) {
         T a[NA], bb[NB];
         monomials<LA, T>(xa, ya, za, a);
-        monomials<LB, T>(xa + abx, ya + aby, za + abz, bb);
+        monomials<LB, T>(xb, yb, zb, bb);
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const T fa = f * a[i];
@@ -948,7 +986,8 @@ k_grad(SegTable<PairSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
-    T *te, *td;
+    PtXY<T> *txy;
+    PtZ<T> *tz;
     AxisBlock *bl;
     int *cnt;
     BlockRow *rows;
@@ -956,20 +995,18 @@ k_grad(SegTable<PairSeg> tab)
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const LevelGeom &G = sg.G;
-    const int wmax = sg.wmax, n_ao = sg.n_ao, emax = sg.emax;
+    const int n_ao = sg.n_ao, emax = sg.emax;
     const double *__restrict__ Vb = sg.Vb;
-    PairSmem<T>::carve(smem_raw, wmax, emax, te, td, bl, cnt, rows);
+    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
-    pair_setup<T>(r, G, te, td, wmax, bl, emax, cnt);
+    pair_setup<T>(r, G, txy, tz, bl, emax, cnt);
     __syncthreads();
-    const int nrows = build_rows(r.R2 * kCullSlack, G, bl, emax, cnt, rows);
+    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
     __syncthreads();
     T gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-    const T abx = (T)r.AB[0], aby = (T)r.AB[1], abz = (T)r.AB[2];
     const T two_aa = (T)(2.0 * r.aa), two_ab = (T)(2.0 * r.ab);
     const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
-    for_each_point<T>(r, te, td, wmax, bl, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za) {
-        const T xb = xa + abx, yb = ya + aby, zb = za + abz;
+    for_each_point<T>(r, txy, tz, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za, T xb, T yb, T zb) {
         T a[NA], bb[NB], t[NA], sv[NB];
         monomials<LA, T>(xa, ya, za, a);
         monomials<LB, T>(xb, yb, zb, bb);
@@ -1061,6 +1098,18 @@ struct SegList {
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Blocks per (x, y) column of a level's block copy: the level's nb2 plus
+// enough periodic repeats that a z run of the plan's longest block list
+// starting anywhere in the cell stays inside the column.
+static int block_column(const gpw_plan_s *pl, int l)
+{
+    return pl->geom[l].nb[2] + std::max(1, pl->max_axis_blocks) - 1;
+}
+static long long block_copy_blocks(const gpw_plan_s *pl, int l)
+{
+    return (long long)pl->geom[l].nb[0] * pl->geom[l].nb[1] * block_column(pl, l);
+}
+
 // Scratch of one task inside the batch's stream-ordered allocation.
 struct TaskScratch {
     size_t dpk = 0, ds = 0, vb = 0;      // byte offsets
@@ -1073,7 +1122,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
 {
     std::vector<TaskScratch> ts(n);
     size_t bytes = 0;
-    int wmax_all = 8, emax_all = 1;
+    int emax_all = 1;
     for (int i = 0; i < n; ++i) {
         const TaskRef &t = tasks[i];
         const gpw_plan_s *pl = t.pl;
@@ -1091,11 +1140,10 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
             long long tot = 0;
             for (int l = 0; l < pl->nlevels; ++l) {
                 x.voff[l] = tot;
-                tot += pl->nblocks[l] * 64;
+                tot += block_copy_blocks(pl, l) * 64;
             }
             x.vb = bytes;
-            bytes += align256(sizeof(double) * (size_t)tot);
-            wmax_all = std::max(wmax_all, pl->info.max_box_width + 8);
+            bytes += align256(sizeof(double) * (size_t)(tot + 64 * kBlockCopyTail));
             emax_all = std::max(emax_all, pl->max_axis_blocks);
             if (t.op == GPW_OP_GRAD) {
                 x.ds = bytes;
@@ -1121,8 +1169,9 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
         const long long cnt = t.op == GPW_OP_MAT ? (long long)pl->n_ao * pl->n_ao : 3LL * pl->natm;
         fills.add({0, t.out, cnt}, nb256(cnt));
         for (int l = 0; l < pl->nlevels; ++l) {
-            const long long m = pl->nblocks[l] * 64;
-            grids.add({0, t.v[l], (double *)(scr + ts[i].vb) + ts[i].voff[l], m, pl->geom[l]}, nb256(m));
+            const long long m = block_copy_blocks(pl, l) * 64;
+            grids.add({0, t.v[l], (double *)(scr + ts[i].vb) + ts[i].voff[l], m, block_column(pl, l), pl->geom[l]},
+                      nb256(m));
         }
         if (t.op == GPW_OP_GRAD && pl->n_ao > 0) {
             const int nt = (pl->n_ao + 31) / 32;
@@ -1146,7 +1195,6 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
         for (int i = 0; i < n; ++i) {
             const TaskRef &t = tasks[i];
             const gpw_plan_s *pl = t.pl;
-            const int wmax = pl->info.max_box_width + 8;
             const int emax = std::max(1, pl->max_axis_blocks);
             for (int l = 0; l < pl->nlevels; ++l) {
                 const int g = l * kNCls + c;
@@ -1177,14 +1225,14 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
                     q.Vb = (const double *)(scr + ts[i].vb) + ts[i].voff[l];
                     q.out = t.out;
                     q.n_ao = pl->n_ao;
-                    q.wmax = wmax;
                     q.emax = emax;
+                    q.vz = block_column(pl, l);
                     q.G = pl->geom[l];
                     (t.op == GPW_OP_MAT ? mats : grads).add(q, np);
                 }
             }
         }
-        const size_t smem = PairSmem<T>::bytes(wmax_all, emax_all);
+        const size_t smem = PairSmem<T>::bytes(emax_all);
         dispatch_cls(c, [&](auto la, auto lb) {
             constexpr int LA = decltype(la)::value, LB = decltype(lb)::value;
             constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
@@ -1212,9 +1260,9 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
     return e;
 }
 
-size_t pair_kernel_lds_bytes(int wmax, int emax, int precision)
+size_t pair_kernel_lds_bytes(int emax, int precision)
 {
-    return precision == GPW_FP32 ? PairSmem<float>::bytes(wmax, emax) : PairSmem<double>::bytes(wmax, emax);
+    return precision == GPW_FP32 ? PairSmem<float>::bytes(emax) : PairSmem<double>::bytes(emax);
 }
 
 hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st)

@@ -278,6 +278,6 @@ struct TaskRef {
 };
 hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st);
 // LDS bytes a workgroup of the pair-major kernels (mat, grad) needs for a plan
-// whose widest box has wmax points (incl. padding) and longest axis block list emax.
-size_t pair_kernel_lds_bytes(int wmax, int emax, int precision);
+// whose longest per-axis block list of a pair image has emax entries.
+size_t pair_kernel_lds_bytes(int emax, int precision);
 }  // namespace gpw
