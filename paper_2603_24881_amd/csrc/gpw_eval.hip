@@ -653,12 +653,14 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int N = G.N[d], nb = G.nb[d];
-        const int g0 = axis_block_id(r.lo[d], N, nb);
-        const int n = axis_block_count(r.lo[d], r.hi[d], N, nb);
+        const int k0 = r.bk0[d], s0 = r.bs0[d], n = r.bn[d];
+        // entry e: wrapped block k0 + e folded into [0, nb), shift s0 + folds
         for (int e = threadIdx.x; e < n; e += 64) {
-            const int gi = g0 + e;
-            const int S = floordiv(gi, nb);
-            const int k = gi - S * nb;
+            int k = k0 + e, S = s0;
+            while (k >= nb) {
+                k -= nb;
+                ++S;
+            }
             const int u0 = 4 * k + S * N;
             const int u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
             AxisBlock eb;
@@ -670,9 +672,12 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
         // points of the entries; a partial block's padding points get the
         // coordinates past the period's end (their potential is zero)
         for (int i = threadIdx.x; i < 4 * n; i += 64) {
-            const int gi = g0 + (i >> 2);
-            const int S = floordiv(gi, nb);
-            const int u = 4 * (gi - S * nb) + (i & 3) + S * N;
+            int k = k0 + (i >> 2), S = s0;
+            while (k >= nb) {
+                k -= nb;
+                ++S;
+            }
+            const int u = 4 * k + (i & 3) + S * N;
             const double x = (double)u * G.h[d];
             const double dx = x - r.P[d];
             const double e = exp(-ap * dx * dx), a = x - r.A[d];
@@ -682,26 +687,12 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
                 tz[i] = PtZ<T>{(T)e, (T)a, (T)(a + r.AB[2]), T(0)};
             }
         }
-        if (threadIdx.x == 0) cnt[d] = n;
-        if (d == 2) {
-            // first z entry whose upper end reaches P: the gaps fall before it
-            // and rise from it on
-            int em = n;
-            for (int e0 = 0; e0 < n && em == n; e0 += 64) {
-                const int e = e0 + (int)threadIdx.x;
-                bool f = false;
-                if (e < n) {
-                    const int gi = g0 + e;
-                    const int S = floordiv(gi, nb);
-                    const int k = gi - S * nb;
-                    const int u1 = (4 * k + 3 < N - 1 ? 4 * k + 3 : N - 1) + S * N;
-                    f = (double)u1 * G.h[2] >= r.P[2];
-                }
-                const unsigned long long m = __ballot(f);
-                if (m) em = e0 + __ffsll((long long)m) - 1;
-            }
-            if (threadIdx.x == 0) cnt[3] = em;
-        }
+    }
+    if (threadIdx.x == 0) {
+        cnt[0] = r.bn[0];
+        cnt[1] = r.bn[1];
+        cnt[2] = r.bn[2];
+        cnt[3] = r.bem;
     }
 }
 
@@ -746,13 +737,15 @@ __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, 
     const int lane = threadIdx.x;
     const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]), em = uni(cnt[3]);
     const AxisBlock *blx = bl, *bly = bl + emax, *blz = bl + 2 * emax;
+    const float rny = 1.0f / (float)ny;
     int nrows = 0;
     for (int base = 0; base < nx * ny; base += 64) {
         const int i = base + lane;
         bool ok = false;
         BlockRow row;
         if (i < nx * ny) {
-            const int ex = i / ny, ey = i - ex * ny;
+            // i / ny in single precision: exact while i and ny stay far below 2^20
+            const int ex = (int)(((float)i + 0.5f) * rny), ey = i - ex * ny;
             const double g = blx[ex].gap2 + bly[ey].gap2;
             if (g <= R2c) {
                 const double rem = R2c - g;

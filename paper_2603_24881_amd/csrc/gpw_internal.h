@@ -36,7 +36,11 @@ struct alignas(64) PairRec {
     double R2;        // squared truncation radius
     double ER;        // exp(-(a+b) R^2): point kept iff envelope >= ER
     double c[3];      // exp(-(a+b) h_d^2) on the pair's level (grid-step factor)
-    double pad[6];
+    // the 4x4x4 blocks the bounding box meets, per axis: the first one's
+    // wrapped index k0 and period shift s0 (unwrapped = k0 + s0 nb), their
+    // count n, and the first z entry whose upper end reaches P (em)
+    int bk0[3], bs0[3], bn[3], bem;
+    int bpad[2];
     int ao_a, ao_b;   // first AO of each shell
     int atom_a, atom_b;
     int lo[3], hi[3]; // unwrapped bounding box of the sphere on the pair's level

@@ -119,7 +119,23 @@ k_pairs(PsTable ps, PlanConst pc, unsigned long long *group_cnt, const long long
                 r.R2 = R * R;
                 r.ER = exp(-ap * R * R);
                 for (int d = 0; d < 3; ++d) r.c[d] = exp(-ap * G.h[d] * G.h[d]);
-                for (int d = 0; d < 6; ++d) r.pad[d] = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    const int g0 = axis_block_id(r.lo[d], G.N[d], G.nb[d]);
+                    r.bs0[d] = floordiv(g0, G.nb[d]);
+                    r.bk0[d] = g0 - r.bs0[d] * G.nb[d];
+                    r.bn[d] = axis_block_count(r.lo[d], r.hi[d], G.N[d], G.nb[d]);
+                }
+                {
+                    // the z gaps fall before this entry and rise from it on
+                    int e = 0, k = r.bk0[2], S = r.bs0[2];
+                    for (; e < r.bn[2]; ++e) {
+                        const int u1 = (4 * k + 3 < G.N[2] - 1 ? 4 * k + 3 : G.N[2] - 1) + S * G.N[2];
+                        if ((double)u1 * G.h[2] >= r.P[2]) break;
+                        if (++k == G.nb[2]) { k = 0; ++S; }
+                    }
+                    r.bem = e;
+                }
+                r.bpad[0] = r.bpad[1] = 0;
                 r.ao_a = ps.ao[fa];
                 r.ao_b = ps.ao[fb];
                 r.atom_a = ps.atom[fa];
