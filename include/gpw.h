@@ -125,10 +125,14 @@ typedef struct {
     long long n_incidences[GPW_MAX_LEVELS];   /* (pair image, 4^3 block) incidences */
     long long n_incidences_class[GPW_NCLASS];
     double sphere_points;                     /* sum over pair images of points inside the sphere */
-    /* flop model (FMA = 2): per (pair image, point), with n_a, n_b the Cartesian counts,
-       F_rho = F_mat = 2 n_a n_b + 2 (n_a + n_b) + 4, F_grad = 4 n_a n_b + 8 (n_a + n_b) + 4.
-       "block" counts 64 points per (pair image, 4^3 block) incidence (the work the
-       grid-block kernels perform); "sphere" counts only points inside the sphere. */
+    /* flop model (FMA = 2).  "sphere": the direct evaluation over the points inside the
+       truncation spheres, per (pair image, point) with n_a, n_b the Cartesian counts
+       F_rho = F_mat = 2 n_a n_b + 2 (n_a + n_b) + 4, F_grad = 4 n_a n_b + 8 (n_a + n_b) + 4
+       (the problem's work, whatever the kernels do).  "block": the arithmetic the kernels
+       perform, over all 64 points of every (pair image, 4^3 block) incidence: the direct
+       per-point F for mat, grad and the rho classes evaluated directly; for the rho classes
+       evaluated through the coefficient tensor (Eq. (rho1)), L = l_a + l_b, per incidence
+       8 C(L+2,3) + 32 C(L+1,2) + 16 + 64 (2L + 3). */
     double flops_rho_block, flops_rho_sphere;
     double flops_mat_block, flops_mat_sphere;
     double flops_grad_block, flops_grad_sphere;

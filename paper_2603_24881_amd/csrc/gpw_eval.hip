@@ -27,6 +27,8 @@
 // same kernels in the same order.
 #include "gpw_internal.h"
 
+#include <utility>
+
 namespace gpw {
 
 // ------------------------------------------------------- segment tables
@@ -90,6 +92,53 @@ struct PairSeg {
 
 // Index of (lx, ly, lz) inside its shell, lexicographic order lx desc, ly desc.
 __host__ __device__ constexpr int cart_index(int ly, int lz) { return (ly + lz) * (ly + lz + 1) / 2 + lz; }
+// Components of the n-th Cartesian function of a shell of degree L.
+__host__ __device__ constexpr int cart_ly(int L, int n)
+{
+    int lx = L;
+    while (n > L - lx) {
+        n -= L - lx + 1;
+        --lx;
+    }
+    return L - lx - n;
+}
+__host__ __device__ constexpr int cart_lx(int L, int n)
+{
+    int lx = L;
+    while (n > L - lx) {
+        n -= L - lx + 1;
+        --lx;
+    }
+    return lx;
+}
+__host__ __device__ constexpr int binom(int n, int k)
+{
+    int b = 1;
+    for (int i = 0; i < k; ++i) b = b * (n - i) / (i + 1);
+    return b;
+}
+
+// Coefficient tensor of a pair image (Sec. III.A, Eqs. (binomial), (rho1)):
+// with every product of a Cartesian function on A and one on B written as a
+// polynomial in r - A (the factor (x - B_x)^b expanded binomially around A),
+// a pair image's density or potential moments live on the monomials
+// (x-A_x)^lx (y-A_y)^ly (z-A_z)^lz of total degree <= L = l_a + l_b.  They are
+// packed lx-major, then ly, then lz: ntab(L) entries.
+__host__ __device__ constexpr int tidx(int L, int lx, int ly, int lz)
+{
+    int n = 0;
+    for (int a = 0; a < lx; ++a) n += (L - a + 1) * (L - a + 2) / 2;
+    for (int b = 0; b < ly; ++b) n += L - lx - b + 1;
+    return n + lz;
+}
+// (ly, lz) pairs of total degree <= L, ly-major
+__host__ __device__ constexpr int ntab2(int L) { return (L + 1) * (L + 2) / 2; }
+__host__ __device__ constexpr int t2idx(int L, int ly, int lz)
+{
+    int n = 0;
+    for (int b = 0; b < ly; ++b) n += L - b + 1;
+    return n + lz;
+}
 
 template <int L, typename T>
 __device__ __forceinline__ void monomials(T x, T y, T z, T *m)
@@ -228,21 +277,21 @@ __device__ __forceinline__ void reduce_points(const T *acc, double (*red)[65], i
     }
 }
 
-// Elements per packed D sub-block: n_a n_b padded to a multiple of 16 bytes
-// (the rho kernel copies sub-blocks in 16-byte pieces).
+// Elements per packed per-pair coefficient set of nc values, padded to a
+// multiple of 16 bytes (the rho kernel copies them in 16-byte pieces).
 template <typename T>
-__host__ __device__ constexpr int dstride(int na, int nb)
+__host__ __device__ constexpr int cstride(int nc)
 {
-    return (na * nb * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
+    return (nc * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
 }
+
 
 // Kw-scaled, symmetrised D sub-blocks of every pair image of one (level,
 // class) group, packed per pair image (n_a n_b values each, padded to 16
-// bytes), so that the rho kernel reads a pair image's D and geometry in one
-// round of loads.
+// bytes), for the classes evaluated directly.
 template <typename T, int NA, int NB>
 __global__ void __launch_bounds__(256)
-k_pack_density(SegTable<PackSeg> tab)
+k_pack_direct(SegTable<PackSeg> tab)
 {
     const PackSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long e = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
@@ -255,7 +304,66 @@ k_pack_density(SegTable<PackSeg> tab)
     const int i = ij / NB, j = ij % NB;
     const PairRec &r = sg.pairs[lp];
     const long long a = r.ao_a + i, b = r.ao_b + j;
-    out[lp * dstride<T>(NA, NB) + ij] = (T)(r.Kw * 0.5 * (D[a * n + b] + D[b * n + a]));
+    out[lp * cstride<T>(NA * NB) + ij] = (T)(r.Kw * 0.5 * (D[a * n + b] + D[b * n + a]));
+}
+
+// One (i, j) element's share of a pair image's density coefficient tensor:
+// d_ij (x-A)^a (x-B)^b with (x - B_x)^b_x = sum_k binom(b_x, k) (x - A_x)^k
+// (A_x - B_x)^(b_x - k) per axis (Eq. (binomial)).
+template <int LA, int LB, int I, int J>
+__device__ __forceinline__ void pack_term(double *C, double dij, const double (*ab)[LB + 1])
+{
+    constexpr int L = LA + LB;
+    constexpr int ax = cart_lx(LA, I), ay = cart_ly(LA, I), az = LA - ax - ay;
+    constexpr int bx = cart_lx(LB, J), by = cart_ly(LB, J), bz = LB - bx - by;
+#pragma unroll
+    for (int kx = 0; kx <= bx; ++kx)
+#pragma unroll
+        for (int ky = 0; ky <= by; ++ky)
+#pragma unroll
+            for (int kz = 0; kz <= bz; ++kz) {
+                const double w = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * ab[0][bx - kx] *
+                                 ab[1][by - ky] * ab[2][bz - kz];
+                C[tidx(L, ax + kx, ay + ky, az + kz)] += w * dij;
+            }
+}
+template <int LA, int LB, int... E>
+__device__ __forceinline__ void pack_terms(std::integer_sequence<int, E...>, double *C, const double *D, long long n,
+                                           long long a0, long long b0, double h, const double (*ab)[LB + 1])
+{
+    constexpr int NB = ncart_c(LB);
+    ((pack_term<LA, LB, E / NB, E % NB>(
+         C, h * (D[(a0 + E / NB) * n + b0 + E % NB] + D[(b0 + E % NB) * n + a0 + E / NB]), ab)),
+     ...);
+}
+
+// Density coefficient tensors of every pair image of one (level, class)
+// group, one thread per pair image (Eqs. (binomial), (rho1)): the Kw-scaled
+// symmetrised D sub-block contracted with the binomial expansion of the B
+// factors around A, in FP64, packed per pair image.
+template <typename T, int LA, int LB>
+__global__ void __launch_bounds__(256)
+k_pack_density(SegTable<PackSeg> tab)
+{
+    constexpr int NA = ncart_c(LA), NB = ncart_c(LB), L = LA + LB, K = ntab(L);
+    const PackSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long lp = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
+    if (lp >= sg.count) return;
+    T *__restrict__ out = (T *)sg.out + lp * cstride<T>(K);
+    const PairRec &r = sg.pairs[lp];
+    double ab[3][LB + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ab[d][0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * r.AB[d];
+    }
+    double C[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) C[k] = 0.0;
+    pack_terms<LA, LB>(std::make_integer_sequence<int, NA * NB>{}, C, sg.D, sg.n, r.ao_a, r.ao_b, 0.5 * r.Kw, ab);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = (T)C[k];
 }
 
 // Per-lane state of one pair image in the rho kernel.  The record and the D
@@ -263,19 +371,19 @@ k_pack_density(SegTable<PackSeg> tab)
 // LDS (16-byte direct-to-LDS loads, one instruction per 16-byte piece for
 // the whole wave, piece c of lane l at c * 1024 + l * 16), so the copy needs
 // no registers while the current batch is computed.
-template <typename T, int NA, int NB>
+template <typename T, int K>
 struct RhoLane {
-    static constexpr int DB = dstride<T>(NA, NB) * (int)sizeof(T);   // bytes of a D sub-block
+    static constexpr int DB = cstride<T>(K) * (int)sizeof(T);         // bytes of a coefficient set
     static constexpr int NCH = 8 + DB / 16;                          // 16-byte pieces per lane
     static constexpr int STAGE = NCH * 1024;                         // LDS bytes of a batch
     double A[3], AB[3], P[3], c[3];
     double ap, ER;
-    T Dk[NA * NB];
+    T Ct[K];
     static __device__ __forceinline__ void stage(const RhoRec *__restrict__ rr, const T *__restrict__ Dpk, int lp,
                                                  unsigned char *lds)
     {
         const unsigned char *gr = reinterpret_cast<const unsigned char *>(rr + lp);
-        const unsigned char *gd = reinterpret_cast<const unsigned char *>(Dpk + (long long)lp * dstride<T>(NA, NB));
+        const unsigned char *gd = reinterpret_cast<const unsigned char *>(Dpk + (long long)lp * cstride<T>(K));
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             __builtin_amdgcn_global_load_lds((const void *)(gr + 16 * k),
@@ -291,7 +399,7 @@ struct RhoLane {
                                                       int lp, unsigned char *lds, int k0, int k1)
     {
         const unsigned char *gr = reinterpret_cast<const unsigned char *>(rr + lp);
-        const unsigned char *gd = reinterpret_cast<const unsigned char *>(Dpk + (long long)lp * dstride<T>(NA, NB));
+        const unsigned char *gd = reinterpret_cast<const unsigned char *>(Dpk + (long long)lp * cstride<T>(K));
 #pragma unroll
         for (int k = 0; k < NCH; ++k) {
             if (k < k0 || k >= k1) continue;
@@ -313,9 +421,9 @@ struct RhoLane {
         }
         ap = r.ap;
         ER = r.ER;
-        const T *src = Dpk + (long long)lp * dstride<T>(NA, NB);
+        const T *src = Dpk + (long long)lp * cstride<T>(K);
 #pragma unroll
-        for (int k = 0; k < NA * NB; ++k) Dk[k] = src[k];
+        for (int k = 0; k < K; ++k) Ct[k] = src[k];
     }
     __device__ __forceinline__ void load(const unsigned char *lds, int lane)
     {
@@ -337,10 +445,127 @@ struct RhoLane {
         ER = r[11];
         constexpr int PER = 16 / (int)sizeof(T);
 #pragma unroll
-        for (int k = 0; k < NA * NB; ++k)
-            Dk[k] = *reinterpret_cast<const T *>(lds + (8 + k / PER) * 1024 + lane * 16 + (k % PER) * sizeof(T));
+        for (int k = 0; k < K; ++k)
+            Ct[k] = *reinterpret_cast<const T *>(lds + (8 + k / PER) * 1024 + lane * 16 + (k % PER) * sizeof(T));
     }
 };
+
+// Density contributions of one lane's pair image to NX x-slices (x points
+// tx0 .. tx0 + NX - 1) of a block: rho(r) += E(r) sum_k Ct_k (r-A)^k with
+// the envelope E = fx fy fz cut at ER.  The polynomial is evaluated by
+// Horner's rule one axis at a time: per x point its coefficients in (y, z),
+// per (x, y) column those in z, per point the z polynomial (Eq. (rho1)).
+template <int L, int NX, typename T>
+__device__ __forceinline__ void rho_points(const T *Ct, double xa0, double ya0, double za0, const LevelGeom &G,
+                                           const double *fx, const double *fy, const double *fz, T ER, T on,
+                                           int tx0, T *acc)
+{
+    T zat[4], fzt[4];   // z offsets and factors, the same for every column
+#pragma unroll
+    for (int tz = 0; tz < 4; ++tz) {
+        zat[tz] = (T)(za0 + tz * G.h[2]);
+        fzt[tz] = (T)fz[tz];
+    }
+#pragma unroll
+    for (int ix = 0; ix < NX; ++ix) {
+        const T xa = (T)(xa0 + (tx0 + ix) * G.h[0]);
+        const T ex = (T)fx[ix] * on;
+        T cyz[ntab2(L)];
+#pragma unroll
+        for (int ly = 0; ly <= L; ++ly)
+#pragma unroll
+            for (int lz = 0; ly + lz <= L; ++lz) {
+                const int top = L - ly - lz;
+                T v = Ct[tidx(L, top, ly, lz)];
+#pragma unroll
+                for (int lx = top - 1; lx >= 0; --lx) v = v * xa + Ct[tidx(L, lx, ly, lz)];
+                cyz[t2idx(L, ly, lz)] = v;
+            }
+#pragma unroll
+        for (int ty = 0; ty < 4; ++ty) {
+            const T ya = (T)(ya0 + ty * G.h[1]);
+            const T exy = ex * (T)fy[ty];
+            T cz[L + 1];
+#pragma unroll
+            for (int lz = 0; lz <= L; ++lz) {
+                const int top = L - lz;
+                T v = cyz[t2idx(L, top, lz)];
+#pragma unroll
+                for (int ly = top - 1; ly >= 0; --ly) v = v * ya + cyz[t2idx(L, ly, lz)];
+                cz[lz] = v;
+            }
+            // the four points of the column side by side: independent chains
+            T E[4], q[4];
+#pragma unroll
+            for (int tz = 0; tz < 4; ++tz) {
+                E[tz] = exy * fzt[tz];
+                q[tz] = cz[L];
+            }
+#pragma unroll
+            for (int lz = L - 1; lz >= 0; --lz)
+#pragma unroll
+                for (int tz = 0; tz < 4; ++tz) q[tz] = q[tz] * zat[tz] + cz[lz];
+#pragma unroll
+            for (int tz = 0; tz < 4; ++tz) acc[ix * 16 + ty * 4 + tz] += ((E[tz] >= ER) ? E[tz] : T(0)) * q[tz];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The same contributions evaluated directly: rho(r) += E(r) sum_ij D_ij
+// a_i(r - A) b_j(r - B), with the Kw-scaled symmetrised D sub-block Dk.
+template <int LA, int LB, int NX, typename T>
+__device__ __forceinline__ void rho_points_direct(const T *Dk, double xa0, double ya0, double za0, const double *AB,
+                                                  const LevelGeom &G, const double *fx, const double *fy,
+                                                  const double *fz, T ER, T on, int tx0, T *acc)
+{
+    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
+    const T abx = (T)AB[0], aby = (T)AB[1], abz = (T)AB[2];
+#pragma unroll
+    for (int ix = 0; ix < NX; ++ix) {
+        const T xa = (T)(xa0 + (tx0 + ix) * G.h[0]);
+        const T xb = xa + abx;
+        const T ex = (T)fx[ix] * on;
+#pragma unroll
+        for (int ty = 0; ty < 4; ++ty) {
+            const T ya = (T)(ya0 + ty * G.h[1]);
+            const T yb = ya + aby;
+            const T exy = ex * (T)fy[ty];
+#pragma unroll
+            for (int tz = 0; tz < 4; ++tz) {
+                const T za = (T)(za0 + tz * G.h[2]);
+                const T zb = za + abz;
+                T E = exy * (T)fz[tz];
+                E = (E >= ER) ? E : T(0);
+                T a[NA], bb[NB];
+                monomials<LA, T>(xa, ya, za, a);
+                monomials<LB, T>(xb, yb, zb, bb);
+                T sum = T(0);
+#pragma unroll
+                for (int i = 0; i < NA; ++i) {
+                    T t = T(0);
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb) t += Dk[i * NB + jb] * bb[jb];
+                    sum += a[i] * t;
+                }
+                acc[ix * 16 + ty * 4 + tz] += E * sum;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// One lane's contributions, in the form the class uses.
+template <int LA, int LB, int NX, typename T>
+__device__ __forceinline__ void rho_lane_points(const T *C, double xa0, double ya0, double za0, const double *AB,
+                                                const LevelGeom &G, const double *fx, const double *fy,
+                                                const double *fz, T ER, T on, int tx0, T *acc)
+{
+    if constexpr (rho_tensor(LA, LB))
+        rho_points<LA + LB, NX, T>(C, xa0, ya0, za0, G, fx, fy, fz, ER, on, tx0, acc);
+    else
+        rho_points_direct<LA, LB, NX, T>(C, xa0, ya0, za0, AB, G, fx, fy, fz, ER, on, tx0, acc);
+}
 
 // Density of one (level, class) group on its nonempty 4x4x4 blocks.  One wave
 // per block; lane = pair image of the block's list (batches of 64), as in
@@ -355,10 +580,9 @@ template <int LA, int LB, int NPASS, int WPE, bool STG, typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_rho(SegTable<RhoSeg> tab)
 {
-    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     constexpr int NX = 4 / NPASS;
     constexpr int NP = 16 * NX;
-    using Lane = RhoLane<T, NA, NB>;
+    using Lane = RhoLane<T, rho_ncoef(LA, LB)>;
     constexpr int LDSB = STG && Lane::STAGE > 32 * 65 * 8 ? Lane::STAGE : 32 * 65 * 8;
     // the batch staging area, and after the last batch the reduction buffer
     __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
@@ -418,40 +642,15 @@ k_rho(SegTable<RhoSeg> tab)
             const T ER = (T)cur.ER;
             const T on = act ? T(1) : T(0);
             const double xa0 = x0 - cur.A[0], ya0 = y0 - cur.A[1], za0 = z0 - cur.A[2];
-            const T abx = (T)cur.AB[0], aby = (T)cur.AB[1], abz = (T)cur.AB[2];
+            double fxp[NX];   // this pass's x factors
 #pragma unroll
             for (int ix = 0; ix < NX; ++ix) {
-                const int tx = pass * NX + ix;
-                const T xa = (T)(xa0 + tx * G.h[0]);
-                const T xb = xa + abx;
-                const T ex = (T)fx[tx] * on;
+                fxp[ix] = fx[ix];
 #pragma unroll
-                for (int ty = 0; ty < 4; ++ty) {
-                    const T ya = (T)(ya0 + ty * G.h[1]);
-                    const T yb = ya + aby;
-                    const T exy = ex * (T)fy[ty];
-#pragma unroll
-                    for (int tz = 0; tz < 4; ++tz) {
-                        const T za = (T)(za0 + tz * G.h[2]);
-                        const T zb = za + abz;
-                        T E = exy * (T)fz[tz];
-                        E = (E >= ER) ? E : T(0);
-                        T a[NA], bb[NB];
-                        monomials<LA, T>(xa, ya, za, a);
-                        monomials<LB, T>(xb, yb, zb, bb);
-                        T sum = T(0);
-#pragma unroll
-                        for (int i = 0; i < NA; ++i) {
-                            T t = T(0);
-#pragma unroll
-                            for (int jb = 0; jb < NB; ++jb) t += cur.Dk[i * NB + jb] * bb[jb];
-                            sum += a[i] * t;
-                        }
-                        acc[ix * 16 + ty * 4 + tz] += E * sum;
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                for (int q = 1; q < NPASS; ++q)
+                    if (pass == q) fxp[ix] = fx[q * NX + ix];
             }
+            rho_lane_points<LA, LB, NX, T>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on, pass * NX, acc);
         }
         reduce_points<NP, T>(acc, red, pass * NP, mine);
     }
@@ -472,8 +671,7 @@ template <int LA, int LB, int WPE, typename T>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_rho2(SegTable<RhoSeg> tab)
 {
-    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
-    using Lane = RhoLane<T, NA, NB>;
+    using Lane = RhoLane<T, rho_ncoef(LA, LB)>;
     constexpr int SB = Lane::STAGE;
     constexpr int REDB = 2 * 32 * 65 * 8;
     constexpr int LDSB = 2 * SB > REDB ? 2 * SB : REDB;
@@ -527,40 +725,8 @@ k_rho2(SegTable<RhoSeg> tab)
         const T ER = (T)cur.ER;
         const T on = act ? T(1) : T(0);
         const double xa0 = x0 - cur.A[0], ya0 = y0 - cur.A[1], za0 = z0 - cur.A[2];
-        const T abx = (T)cur.AB[0], aby = (T)cur.AB[1], abz = (T)cur.AB[2];
-#pragma unroll
-        for (int ix = 0; ix < 2; ++ix) {
-            const int tx = 2 * w + ix;
-            const T xa = (T)(xa0 + tx * G.h[0]);
-            const T xb = xa + abx;
-            const T ex = (T)(w ? fx[2 + ix] : fx[ix]) * on;
-#pragma unroll
-            for (int ty = 0; ty < 4; ++ty) {
-                const T ya = (T)(ya0 + ty * G.h[1]);
-                const T yb = ya + aby;
-                const T exy = ex * (T)fy[ty];
-#pragma unroll
-                for (int tz = 0; tz < 4; ++tz) {
-                    const T za = (T)(za0 + tz * G.h[2]);
-                    const T zb = za + abz;
-                    T E = exy * (T)fz[tz];
-                    E = (E >= ER) ? E : T(0);
-                    T a[NA], bb[NB];
-                    monomials<LA, T>(xa, ya, za, a);
-                    monomials<LB, T>(xb, yb, zb, bb);
-                    T sum = T(0);
-#pragma unroll
-                    for (int i = 0; i < NA; ++i) {
-                        T t = T(0);
-#pragma unroll
-                        for (int jb = 0; jb < NB; ++jb) t += cur.Dk[i * NB + jb] * bb[jb];
-                        sum += a[i] * t;
-                    }
-                    acc[ix * 16 + ty * 4 + tz] += E * sum;
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
+        const double fxp[2] = {w ? fx[2] : fx[0], w ? fx[3] : fx[1]};
+        rho_lane_points<LA, LB, 2, T>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on, 2 * w, acc);
     }
     __syncthreads();   // every read of the staging buffers is done
     double mine = 0.0;
@@ -596,7 +762,7 @@ template <> struct RhoSplit<2, 1> {
     static constexpr bool stage = true, two = false;
 };
 template <> struct RhoSplit<2, 2> {
-    static constexpr int npass = 2, wpe = 1, wpe2 = 2;
+    static constexpr int npass = 2, wpe = 2, wpe2 = 2;
     static constexpr bool stage = false, two = false;
 };
 template <> struct RhoSplit<3, 0> {
@@ -1125,7 +1291,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
             for (int g = 0; g < kMaxGroups; ++g) {
                 const int c = g % kNCls;
                 x.dbase[g + 1] = x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) *
-                                                  dstride<T>(ncart(cls_la(c)), ncart(cls_lb(c)));
+                                                  cstride<T>(rho_ncoef(cls_la(c), cls_lb(c)));
             }
             x.dpk = bytes;
             bytes += align256(sizeof(T) * (size_t)x.dbase[kMaxGroups]);
@@ -1195,7 +1361,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
                 const PairRec *pairs = (const PairRec *)pl->d_pairs + pl->group_off[g];
                 if (t.op == GPW_OP_RHO) {
                     T *Dpk = (T *)(scr + ts[i].dpk) + ts[i].dbase[g];
-                    const long long ne = np * ncart(cls_la(c)) * ncart(cls_lb(c));
+                    const long long ne = rho_tensor(cls_la(c), cls_lb(c)) ? np : np * ncart(cls_la(c)) * ncart(cls_lb(c));
                     packs.add({0, pairs, t.D, Dpk, ne, pl->n_ao}, nb256(ne));
                     RhoSeg r;
                     r.item0 = 0;
@@ -1230,7 +1396,10 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
             constexpr int LA = decltype(la)::value, LB = decltype(lb)::value;
             constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
             packs.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
-                hipLaunchKernelGGL((k_pack_density<T, NA, NB>), dim3(g), dim3(256), 0, st, tb);
+                if constexpr (rho_tensor(LA, LB))
+                    hipLaunchKernelGGL((k_pack_density<T, LA, LB>), dim3(g), dim3(256), 0, st, tb);
+                else
+                    hipLaunchKernelGGL((k_pack_direct<T, NA, NB>), dim3(g), dim3(256), 0, st, tb);
             }, false);
             using RS = RhoSplit<LA, LB>;
             rhos.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {

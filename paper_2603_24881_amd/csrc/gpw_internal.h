@@ -24,6 +24,24 @@ __host__ __device__ inline int cls_of(int la, int lb) { return la * (la + 1) / 2
 __host__ __device__ inline int cls_la(int c) { return c >= 6 ? 3 : c >= 3 ? 2 : c >= 1 ? 1 : 0; }
 __host__ __device__ inline int cls_lb(int c) { int la = cls_la(c); return c - la * (la + 1) / 2; }
 
+// Monomials (x-A_x)^lx (y-A_y)^ly (z-A_z)^lz of total degree <= L.
+__host__ __device__ constexpr int ntab(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+
+// Whether the rho kernel of class (la, lb) evaluates a pair image's density
+// through its coefficient tensor (Sec. III.A, Eq. (rho1): ntab(la + lb)
+// values per pair image) or directly as sum_ij D_ij a_i b_j (n_a n_b
+// values): the tensor needs fewer operations per point, the direct form
+// offers more independent operations; chosen per class by measurement on
+// the 256-water system.
+__host__ __device__ constexpr bool rho_tensor(int la, int lb)
+{
+    return la == 2 || (la == 3 && lb >= 1 && lb <= 2);
+}
+__host__ __device__ constexpr int rho_ncoef(int la, int lb)
+{
+    return rho_tensor(la, lb) ? ntab(la + lb) : ncart_c(la) * ncart_c(lb);
+}
+
 // One canonical pair image (unordered pair of primitive shells plus the
 // lattice translation of the second one).  The first factor carries the
 // higher angular momentum.  256 bytes.
