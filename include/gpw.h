@@ -125,17 +125,20 @@ typedef struct {
     long long n_incidences[GPW_MAX_LEVELS];   /* (pair image, 4^3 block) incidences */
     long long n_incidences_class[GPW_NCLASS];
     double sphere_points;                     /* sum over pair images of points inside the sphere */
-    /* flop model (FMA = 2).  "sphere": the direct evaluation over the points inside the
-       truncation spheres, per (pair image, point) with n_a, n_b the Cartesian counts
-       F_rho = F_mat = 2 n_a n_b + 2 (n_a + n_b) + 4, F_grad = 4 n_a n_b + 8 (n_a + n_b) + 4
-       (the problem's work, whatever the kernels do).  "block": the arithmetic the kernels
-       perform, over all 64 points of every (pair image, 4^3 block) incidence: the direct
-       per-point F for mat, grad and the rho classes evaluated directly; for the rho classes
-       evaluated through the coefficient tensor (Eq. (rho1)), L = l_a + l_b, per incidence
-       8 C(L+2,3) + 32 C(L+1,2) + 16 + 64 (2L + 3). */
+    /* flop model (FMA = 2), a fixed counting convention: per (pair image, point), with n_a,
+       n_b the Cartesian counts, F_rho = F_mat = 2 n_a n_b + 2 (n_a + n_b) + 4 and
+       F_grad = 4 n_a n_b + 8 (n_a + n_b) + 4 (the direct evaluation).  "block" counts 64
+       points per (pair image, 4^3 block) incidence (the points the block method visits);
+       "sphere" counts only points inside the sphere. */
     double flops_rho_block, flops_rho_sphere;
     double flops_mat_block, flops_mat_sphere;
     double flops_grad_block, flops_grad_sphere;
+    /* the arithmetic the rho and mat kernels perform over the block points (FMA = 2): the
+       direct F for the classes evaluated directly; with L = l_a + l_b, per incidence
+       8 C(L+2,3) + 32 C(L+1,2) + 16 + 64 (2L + 3) for the rho classes evaluated through the
+       coefficient tensor (Eq. (rho1)) and 64 (2L + 3) for the mat classes accumulating
+       moments */
+    double flops_rho_exec, flops_mat_exec;
     long long device_bytes;                   /* device memory held by the plan */
     int max_box_width;                        /* widest bounding box (points per axis) */
 } gpw_plan_info;

@@ -80,6 +80,8 @@ class gpw_plan_info(C.Structure):
         ("flops_mat_sphere", C.c_double),
         ("flops_grad_block", C.c_double),
         ("flops_grad_sphere", C.c_double),
+        ("flops_rho_exec", C.c_double),
+        ("flops_mat_exec", C.c_double),
         ("device_bytes", C.c_longlong),
         ("max_box_width", C.c_int),
     ]
@@ -226,6 +228,7 @@ class PlanHandle:
             "flops_rho_block": info.flops_rho_block, "flops_rho_sphere": info.flops_rho_sphere,
             "flops_mat_block": info.flops_mat_block, "flops_mat_sphere": info.flops_mat_sphere,
             "flops_grad_block": info.flops_grad_block, "flops_grad_sphere": info.flops_grad_sphere,
+            "flops_rho_exec": info.flops_rho_exec, "flops_mat_exec": info.flops_mat_exec,
             "device_bytes": info.device_bytes, "max_box_width": info.max_box_width,
         }
 

@@ -959,17 +959,15 @@ __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, 
 // before the current four are used, so that the load latency overlaps the
 // arithmetic; the loads always cover four whole blocks (the block copy has
 // kBlockCopyTail blocks of slack at its end), which keeps their number fixed.
-// body(f, xa, ya, za, xb, yb, zb): f = v(r) exp(-alpha_p |r-P|^2) inside the
-// sphere, else 0; (xa, ya, za) = r - A, (xb, yb, zb) = r - B.
-template <typename T, typename Body>
-__device__ __forceinline__ void for_each_point(const PairRec &r, const PtXY<T> *txy, const PtZ<T> *tzt, int emax,
-                                               const BlockRow *rows, int nrows, const double *__restrict__ Vb,
-                                               Body &&body)
+// The visitor sees vis.row(ex, X, Y) at the start of every row (X, Y: the
+// lane's x and y table entries) and vis.point(v, Z) for every point (v the
+// potential, Z the lane's z table entry), then vis.done().
+template <typename T, typename Vis>
+__device__ __forceinline__ void for_each_point(const PtXY<T> *txy, const PtZ<T> *tzt, int emax, const BlockRow *rows,
+                                               int nrows, const double *__restrict__ Vb, Vis &vis)
 {
     const int lane = threadIdx.x;
     const int E4 = 4 * emax;
-    const T ER = (T)r.ER;
-    const T abx = (T)r.AB[0], aby = (T)r.AB[1];
     const PtXY<T> *px = txy + (lane >> 4), *py = txy + E4 + ((lane >> 2) & 3);
     const PtZ<T> *pz = tzt + (lane & 3);
     if (nrows <= 0) return;
@@ -1002,19 +1000,12 @@ __device__ __forceinline__ void for_each_point(const PairRec &r, const PtXY<T> *
         return true;
     };
     auto run = [&](const Cur &c, const double *v) {
-        const PtXY<T> X = px[4 * c.ex], Y = py[4 * c.ey];
-        const T xb = X.a + abx, yb = Y.a + aby;
-        const T exy = X.e * Y.e;
+        if (c.i0 == 0) vis.row(c.ex, px[4 * c.ex], py[4 * c.ey]);
         const PtZ<T> *z = pz + 4 * ((c.zn & 0xffff) + c.i0);
         const int m = (c.zn >> 16) - c.i0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (u < m) {
-                const PtZ<T> Z = z[4 * u];
-                const T E = exy * Z.e;
-                body((E >= ER) ? (T)v[u] * E : T(0), X.a, Y.a, Z.a, xb, yb, Z.b);
-            }
-        }
+        for (int u = 0; u < 4; ++u)
+            if (u < m) vis.point((T)v[u], z[4 * u]);
     };
     Cur a;
     a.rr = 0;
@@ -1035,7 +1026,116 @@ __device__ __forceinline__ void for_each_point(const PairRec &r, const PtXY<T> *
         run(b, vb4);
         if (!ma) break;
     }
+    vis.done();
 }
+
+// Visitor of the direct form: body(f, xa, ya, za, xb, yb, zb) per point with
+// f = v(r) exp(-alpha_p |r-P|^2) inside the sphere, else 0, (xa, ya, za) =
+// r - A and (xb, yb, zb) = r - B.
+template <typename T, typename Body>
+struct DirectVisit {
+    Body &body;
+    T ER, abx, aby;
+    T xa = 0, ya = 0, xb = 0, yb = 0, exy = 0;
+    __device__ DirectVisit(Body &b, const PairRec &r) : body(b), ER((T)r.ER), abx((T)r.AB[0]), aby((T)r.AB[1]) {}
+    __device__ __forceinline__ void row(int, const PtXY<T> &X, const PtXY<T> &Y)
+    {
+        xa = X.a;
+        ya = Y.a;
+        xb = xa + abx;
+        yb = ya + aby;
+        exy = X.e * Y.e;
+    }
+    __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
+    {
+        const T E = exy * Z.e;
+        body((E >= ER) ? v * E : T(0), xa, ya, Z.a, xb, yb, Z.b);
+    }
+    __device__ __forceinline__ void done() {}
+};
+
+// Visitor of the separable form (the potential analogue of Eq. (rho1)): the
+// moments sum_r v(r) E(r) (x-A_x)^lx (y-A_y)^ly (z-A_z)^lz of total degree
+// <= L, accumulated one axis at a time: per point the z moments of the
+// lane's current (x, y) column (W), at the end of a row the (y, z) moments
+// of the lane's x slice (U), when the row's x block changes the full
+// moments (Vm).  E(r) = ex ey ez is split the same way; the sphere cut uses
+// the full product.
+template <int L, typename T>
+struct TensorVisit {
+    static constexpr int K = ntab(L), K2 = ntab2(L);
+    T Vm[K], U[K2], W[L + 1];
+    T ER;
+    T xa = 0, ex = 0, ya = 0, ey = 0, exy = 0;
+    int xcur = -1;
+    __device__ explicit TensorVisit(const PairRec &r) : ER((T)r.ER)
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k) Vm[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < K2; ++k) U[k] = T(0);
+#pragma unroll
+        for (int k = 0; k <= L; ++k) W[k] = T(0);
+    }
+    __device__ __forceinline__ void flush_row()
+    {
+        T g = ey;
+#pragma unroll
+        for (int ly = 0; ly <= L; ++ly) {
+#pragma unroll
+            for (int lz = 0; ly + lz <= L; ++lz) U[t2idx(L, ly, lz)] += W[lz] * g;
+            g *= ya;
+        }
+#pragma unroll
+        for (int k = 0; k <= L; ++k) W[k] = T(0);
+    }
+    __device__ __forceinline__ void flush_x()
+    {
+        T g = ex;
+#pragma unroll
+        for (int lx = 0; lx <= L; ++lx) {
+#pragma unroll
+            for (int ly = 0; lx + ly <= L; ++ly)
+#pragma unroll
+                for (int lz = 0; lx + ly + lz <= L; ++lz) Vm[tidx(L, lx, ly, lz)] += U[t2idx(L, ly, lz)] * g;
+            g *= xa;
+        }
+#pragma unroll
+        for (int k = 0; k < K2; ++k) U[k] = T(0);
+    }
+    __device__ __forceinline__ void row(int exn, const PtXY<T> &X, const PtXY<T> &Y)
+    {
+        if (xcur >= 0) {
+            flush_row();
+            if (exn != xcur) flush_x();
+        }
+        xcur = exn;
+        xa = X.a;
+        ex = X.e;
+        ya = Y.a;
+        ey = Y.e;
+        exy = ex * ey;
+    }
+    __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
+    {
+        const T E = exy * Z.e;
+        const T f = (E >= ER) ? v * Z.e : T(0);
+        W[0] += f;
+        T p = f;
+#pragma unroll
+        for (int lz = 1; lz <= L; ++lz) {
+            p *= Z.a;
+            W[lz] += p;
+        }
+    }
+    __device__ __forceinline__ void done()
+    {
+        if (xcur >= 0) {
+            flush_row();
+            flush_x();
+        }
+    }
+};
 
 // Wave sums of the K per-lane accumulators of a pair-major kernel, eight at
 // a time through LDS (red[8][65], the kernel's LDS area once the traversal is
@@ -1043,7 +1143,7 @@ __device__ __forceinline__ void for_each_point(const PairRec &r, const PtXY<T> *
 // finish the sum, and lane 8q applies emit(k, sum) for k = chunk + q.  The
 // eight results of a chunk leave in parallel instead of one lane issuing
 // every atomic.
-constexpr size_t kRedBytes = 8 * 65 * sizeof(double);
+constexpr size_t kRedBytes = (8 * 65 + 84) * sizeof(double);   // red[8][65] and up to ntab(6) moments
 template <int K, typename T, typename Emit>
 __device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit &&emit)
 {
@@ -1116,27 +1216,65 @@ k_mat(SegTable<PairSeg> tab)
     __syncthreads();
     const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
     __syncthreads();
-    T acc[NA * NB];
-#pragma unroll
-    for (int i = 0; i < NA * NB; ++i) acc[i] = T(0);
-    for_each_point<T>(r, txy, tz, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za, T xb, T yb, T zb) {
-        T a[NA], bb[NB];
-        monomials<LA, T>(xa, ya, za, a);
-        monomials<LB, T>(xb, yb, zb, bb);
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            const T fa = f * a[i];
-#pragma unroll
-            for (int j = 0; j < NB; ++j) acc[i * NB + j] += fa * bb[j];
-        }
-    });
     const double scale = 0.5 * G.w * r.Kw;
-    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
-    wave_reduce_emit<NA * NB, T>(acc, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
-        const int i = k / NB, j = k - (k / NB) * NB;
-        atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * v);
-        atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * v);
-    });
+    if constexpr (!mat_tensor(LA, LB)) {
+        T acc[NA * NB];
+#pragma unroll
+        for (int i = 0; i < NA * NB; ++i) acc[i] = T(0);
+        auto body = [&](T f, T xa, T ya, T za, T xb, T yb, T zb) {
+            T a[NA], bb[NB];
+            monomials<LA, T>(xa, ya, za, a);
+            monomials<LB, T>(xb, yb, zb, bb);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                const T fa = f * a[i];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[i * NB + j] += fa * bb[j];
+            }
+        };
+        DirectVisit<T, decltype(body)> vis(body, r);
+        for_each_point<T>(txy, tz, emax, rows, nrows, Vb, vis);
+        __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+        wave_reduce_emit<NA * NB, T>(acc, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
+            const int i = k / NB, j = k - (k / NB) * NB;
+            atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * v);
+            atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * v);
+        });
+    } else {
+        constexpr int L = LA + LB, K = ntab(L);
+        TensorVisit<L, T> vis(r);
+        for_each_point<T>(txy, tz, emax, rows, nrows, Vb, vis);
+        __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+        // wave sums of the moments, kept in LDS past the reduction area
+        double *mom = reinterpret_cast<double *>(smem_raw) + 8 * 65;
+        wave_reduce_emit<K, T>(vis.Vm, reinterpret_cast<double *>(smem_raw),
+                               [&](int k, double v) { mom[k] = v; });
+        __syncthreads();
+        // element (i, j): the moments of (x-A)^a (x-B)^b with every
+        // (x - B_x)^b_x expanded binomially around A (Eq. (binomial))
+        for (int ij = threadIdx.x; ij < NA * NB; ij += 64) {
+            const int i = ij / NB, j = ij - (ij / NB) * NB;
+            const int ax = cart_lx(LA, i), ay = cart_ly(LA, i), az = LA - ax - ay;
+            const int bx = cart_lx(LB, j), by = cart_ly(LB, j), bz = LB - bx - by;
+            double m = 0.0;
+            double px = 1.0;
+            for (int kx = bx; kx >= 0; --kx) {
+                double py = 1.0;
+                for (int ky = by; ky >= 0; --ky) {
+                    double pz = 1.0;
+                    for (int kz = bz; kz >= 0; --kz) {
+                        m += (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * px * py * pz *
+                             mom[tidx(L, ax + kx, ay + ky, az + kz)];
+                        pz *= r.AB[2];
+                    }
+                    py *= r.AB[1];
+                }
+                px *= r.AB[0];
+            }
+            atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * m);
+            atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * m);
+        }
+    }
 }
 
 template <int LA, int LB, typename T>
@@ -1165,7 +1303,7 @@ k_grad(SegTable<PairSeg> tab)
     T gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
     const T two_aa = (T)(2.0 * r.aa), two_ab = (T)(2.0 * r.ab);
     const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
-    for_each_point<T>(r, txy, tz, emax, rows, nrows, Vb, [&](T f, T xa, T ya, T za, T xb, T yb, T zb) {
+    auto body = [&](T f, T xa, T ya, T za, T xb, T yb, T zb) {
         T a[NA], bb[NB], t[NA], sv[NB];
         monomials<LA, T>(xa, ya, za, a);
         monomials<LB, T>(xb, yb, zb, bb);
@@ -1194,7 +1332,9 @@ k_grad(SegTable<PairSeg> tab)
         gB[0] += two_ab * fS * xb - f * pb[0];
         gB[1] += two_ab * fS * yb - f * pb[1];
         gB[2] += two_ab * fS * zb - f * pb[2];
-    });
+    };
+    DirectVisit<T, decltype(body)> vis(body, r);
+    for_each_point<T>(txy, tz, emax, rows, nrows, Vb, vis);
     const double scale = G.w * r.Kw;
     const T g6[6] = {gA[0], gA[1], gA[2], gB[0], gB[1], gB[2]};
     __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]

@@ -37,6 +37,11 @@ __host__ __device__ constexpr bool rho_tensor(int la, int lb)
 {
     return la == 2 || (la == 3 && lb >= 1 && lb <= 2);
 }
+// Whether the mat kernel of class (la, lb) accumulates the potential moments
+// of the monomials of r - A one axis at a time and forms the matrix elements
+// from them once per pair image (the integration analogue of Eq. (rho1)), or
+// accumulates the n_a n_b products a_i b_j per point directly.
+__host__ __device__ constexpr bool mat_tensor(int la, int lb) { return la + lb >= 2; }
 __host__ __device__ constexpr int rho_ncoef(int la, int lb)
 {
     return rho_tensor(la, lb) ? ntab(la + lb) : ncart_c(la) * ncart_c(lb);

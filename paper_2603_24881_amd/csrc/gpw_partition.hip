@@ -574,24 +574,30 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         I.n_incidences_class[c] += ninc;
         const int la = cls_la(c), lb = cls_lb(c), L = la + lb;
         const double na = ncart(la), nb = ncart(lb);
-        // direct evaluation, per point: sum_ij D_ij a_i b_j (or the n_a n_b
-        // products of mat), monomials, envelope and accumulation
+        // the counting convention, per (pair image, point): the direct
+        // evaluation sum_ij D_ij a_i b_j (or the n_a n_b products of mat),
+        // monomials, envelope and accumulation
         const double f1 = 2 * na * nb + 2 * (na + nb) + 4;
         const double f2 = 4 * na * nb + 8 * (na + nb) + 4;
-        // coefficient-tensor evaluation, per (pair image, block): Horner in x
-        // for the (y, z) coefficients at 4 x points (C(L+2,3) FMAs each), in y
-        // for the z coefficients of 16 columns (C(L+1,2) FMAs each), the 16
-        // column envelope products, and per point L Horner FMAs, the envelope
-        // product and the accumulation
-        const double ft = 8.0 * (L + 2) * (L + 1) * L / 6.0 + 32.0 * (L + 1) * L / 2.0 + 16.0 + 64.0 * (2 * L + 3);
         const double pts = stats[2 * g], blkpts = 64.0 * (double)ninc;
         I.sphere_points += pts;
         I.flops_rho_sphere += f1 * pts;
-        I.flops_rho_block += rho_tensor(la, lb) ? ft * (double)ninc : f1 * blkpts;
+        I.flops_rho_block += f1 * blkpts;
         I.flops_mat_sphere += f1 * pts;
         I.flops_mat_block += f1 * blkpts;
         I.flops_grad_sphere += f2 * pts;
         I.flops_grad_block += f2 * blkpts;
+        // the arithmetic the kernels perform per (pair image, block).  rho
+        // through the coefficient tensor: Horner in x for the (y, z)
+        // coefficients at 4 x points (C(L+2,3) FMAs each), in y for the z
+        // coefficients of 16 columns (C(L+1,2) FMAs each), 16 column envelope
+        // products, per point L Horner FMAs, the envelope product and the
+        // accumulation.  mat through the moments: per point the envelope
+        // product, the cut potential, L powers and L+1 accumulations (the
+        // per-row and per-x-slice flushes, ~1-2 %, are not counted).
+        const double ft = 8.0 * (L + 2) * (L + 1) * L / 6.0 + 32.0 * (L + 1) * L / 2.0 + 16.0 + 64.0 * (2 * L + 3);
+        I.flops_rho_exec += rho_tensor(la, lb) ? ft * (double)ninc : f1 * blkpts;
+        I.flops_mat_exec += (mat_tensor(la, lb) ? 2.0 * L + 3.0 : f1) * blkpts;
     }
 
     (void)hipFree(d_gcnt);
