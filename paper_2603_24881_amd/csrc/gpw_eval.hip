@@ -160,27 +160,6 @@ __device__ __forceinline__ void monomials(T x, T y, T z, T *m)
         }
 }
 
-// g[d] = sum_mu t_mu d(monomial_mu)/d(offset_d) for a shell of degree L.
-template <int L, typename T>
-__device__ __forceinline__ void poly_grad(T x, T y, T z, const T *t, T *g)
-{
-    g[0] = g[1] = g[2] = T(0);
-    if (L == 0) return;
-    T lower[(L + 1) * L / 2 > 0 ? (L + 1) * L / 2 : 1];   // monomials of degree L-1
-    monomials<(L > 0 ? L - 1 : 0), T>(x, y, z, lower);
-    int n = 0;
-#pragma unroll
-    for (int lx = L; lx >= 0; --lx)
-#pragma unroll
-        for (int ly = L - lx; ly >= 0; --ly) {
-            const int lz = L - lx - ly;
-            if (lx) g[0] += T(lx) * t[n] * lower[cart_index(ly, lz)];
-            if (ly) g[1] += T(ly) * t[n] * lower[cart_index(ly - 1, lz)];
-            if (lz) g[2] += T(lz) * t[n] * lower[cart_index(ly, lz - 1)];
-            ++n;
-        }
-}
-
 // --------------------------------------------------------- small kernels
 
 // out = (D + D^T) / 2 through 32x32 LDS tiles (both reads coalesced).
@@ -1143,7 +1122,7 @@ struct TensorVisit {
 // finish the sum, and lane 8q applies emit(k, sum) for k = chunk + q.  The
 // eight results of a chunk leave in parallel instead of one lane issuing
 // every atomic.
-constexpr size_t kRedBytes = (8 * 65 + 84) * sizeof(double);   // red[8][65] and up to ntab(6) moments
+constexpr size_t kRedBytes = (8 * 65 + 120) * sizeof(double);   // red[8][65] and up to ntab(7) moments
 template <int K, typename T, typename Emit>
 __device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit &&emit)
 {
@@ -1282,6 +1261,7 @@ __global__ void __launch_bounds__(64)
 k_grad(SegTable<PairSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
+    constexpr int L1 = LA + LB + 1, K = ntab(L1);
     extern __shared__ unsigned char smem_raw[];
     PtXY<T> *txy;
     PtZ<T> *tz;
@@ -1300,45 +1280,73 @@ k_grad(SegTable<PairSeg> tab)
     __syncthreads();
     const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
     __syncthreads();
-    T gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-    const T two_aa = (T)(2.0 * r.aa), two_ab = (T)(2.0 * r.ab);
-    const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
-    auto body = [&](T f, T xa, T ya, T za, T xb, T yb, T zb) {
-        T a[NA], bb[NB], t[NA], sv[NB];
-        monomials<LA, T>(xa, ya, za, a);
-        monomials<LB, T>(xb, yb, zb, bb);
-#pragma unroll
-        for (int j = 0; j < NB; ++j) sv[j] = T(0);
-        T S0 = T(0);
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            T ti = T(0);
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const T dij = Dp[(long long)i * n_ao + j];
-                ti += dij * bb[j];
-                sv[j] += dij * a[i];
-            }
-            t[i] = ti;
-            S0 += a[i] * ti;
-        }
-        T pa[3], pb[3];
-        poly_grad<LA, T>(xa, ya, za, t, pa);
-        poly_grad<LB, T>(xb, yb, zb, sv, pb);
-        const T fS = f * S0;
-        gA[0] += two_aa * fS * xa - f * pa[0];
-        gA[1] += two_aa * fS * ya - f * pa[1];
-        gA[2] += two_aa * fS * za - f * pa[2];
-        gB[0] += two_ab * fS * xb - f * pb[0];
-        gB[1] += two_ab * fS * yb - f * pb[1];
-        gB[2] += two_ab * fS * zb - f * pb[2];
-    };
-    DirectVisit<T, decltype(body)> vis(body, r);
+    // potential moments of the monomials of r - A up to degree l_a + l_b + 1
+    TensorVisit<L1, T> vis(r);
     for_each_point<T>(txy, tz, emax, rows, nrows, Vb, vis);
-    const double scale = G.w * r.Kw;
-    const T g6[6] = {gA[0], gA[1], gA[2], gB[0], gB[1], gB[2]};
     __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
-    wave_reduce_emit<6, T>(g6, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
+    double *red = reinterpret_cast<double *>(smem_raw);
+    double *mom = red + 8 * 65;
+    wave_reduce_emit<K, T>(vis.Vm, red, [&](int k, double v) { mom[k] = v; });
+    __syncthreads();
+    // lane per element (i, j): with E = exp(-a |r-A|^2 - b |r-B|^2),
+    //   d/dA_d [a_i b_j E] = (2 a (r-A)_d a_i - d_d a_i) b_j E,
+    //   d/dB_d [a_i b_j E] = (2 b (r-B)_d b_j - d_d b_j) a_i E,
+    // both polynomials in r - A once (r - B) = (r - A) + (A - B) is expanded
+    // binomially (Eq. (binomial)); their integrals against v are sums of
+    // moments, weighted by the symmetrised D_ij.
+    const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
+    const double two_a = 2.0 * r.aa, two_b = 2.0 * r.ab;
+    const double AB[3] = {r.AB[0], r.AB[1], r.AB[2]};
+    auto M = [&](int mx, int my, int mz) { return mom[tidx(L1, mx, my, mz)]; };
+    double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int ij = threadIdx.x; ij < NA * NB; ij += 64) {
+        const int i = ij / NB, j = ij - (ij / NB) * NB;
+        const int a[3] = {cart_lx(LA, i), cart_ly(LA, i), LA - cart_lx(LA, i) - cart_ly(LA, i)};
+        const int b[3] = {cart_lx(LB, j), cart_ly(LB, j), LB - cart_lx(LB, j) - cart_ly(LB, j)};
+        const double dij = (double)Dp[(long long)i * n_ao + j];
+        double ga[3] = {0.0, 0.0, 0.0}, gb[3] = {0.0, 0.0, 0.0};
+        // b_j(r - B) = sum_k c_k (r - A)^k
+        for (int kx = 0; kx <= b[0]; ++kx)
+            for (int ky = 0; ky <= b[1]; ++ky)
+                for (int kz = 0; kz <= b[2]; ++kz) {
+                    double c = (double)(binom(b[0], kx) * binom(b[1], ky) * binom(b[2], kz));
+                    for (int e = kx; e < b[0]; ++e) c *= AB[0];
+                    for (int e = ky; e < b[1]; ++e) c *= AB[1];
+                    for (int e = kz; e < b[2]; ++e) c *= AB[2];
+                    const int m[3] = {a[0] + kx, a[1] + ky, a[2] + kz};
+                    const double M0 = M(m[0], m[1], m[2]);
+                    for (int d = 0; d < 3; ++d) {
+                        const double Md = M(m[0] + (d == 0), m[1] + (d == 1), m[2] + (d == 2));
+                        double da = 0.0;   // d_d (r-A)^a_d
+                        if (a[d] > 0) da = a[d] * M(m[0] - (d == 0), m[1] - (d == 1), m[2] - (d == 2));
+                        ga[d] += c * (two_a * Md - da);
+                        gb[d] += c * two_b * (Md + AB[d] * M0);
+                    }
+                }
+        // - a_i d_d b_j(r - B) = - b_d a_i (r - B)^(b - e_d), expanded the same way
+        for (int d = 0; d < 3; ++d) {
+            if (b[d] == 0) continue;
+            int bb[3] = {b[0], b[1], b[2]};
+            bb[d] -= 1;
+            for (int kx = 0; kx <= bb[0]; ++kx)
+                for (int ky = 0; ky <= bb[1]; ++ky)
+                    for (int kz = 0; kz <= bb[2]; ++kz) {
+                        double c = (double)(binom(bb[0], kx) * binom(bb[1], ky) * binom(bb[2], kz));
+                        for (int e = kx; e < bb[0]; ++e) c *= AB[0];
+                        for (int e = ky; e < bb[1]; ++e) c *= AB[1];
+                        for (int e = kz; e < bb[2]; ++e) c *= AB[2];
+                        gb[d] -= b[d] * c * M(a[0] + kx, a[1] + ky, a[2] + kz);
+                    }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            g6[d] += dij * ga[d];
+            g6[3 + d] += dij * gb[d];
+        }
+    }
+    const double scale = G.w * r.Kw;
+    __syncthreads();   // every read of the moments is done
+    wave_reduce_emit<6, double>(g6, red, [&](int k, double v) {
         atomicAdd(&sg.out[3 * (k < 3 ? r.atom_a : r.atom_b) + (k < 3 ? k : k - 3)], scale * v);
     });
 }
