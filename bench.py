@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--cpu-atoms", type=int, default=0, help="atoms in the oracle sample (0 = auto)")
     ap.add_argument("--extras", type=int, default=1, help="also time grad, fp32 and the plan")
     ap.add_argument("--serve-requests", type=int, default=120, help="requests in the serving run (0 = skip)")
-    ap.add_argument("--serve-rates", default="20,100", help="Poisson arrival rates (requests/s), comma-separated")
+    ap.add_argument("--serve-rates", default="20,100,200", help="Poisson arrival rates (requests/s), comma-separated")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters) and exit")

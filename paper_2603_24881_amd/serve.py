@@ -157,11 +157,13 @@ class Scheduler:
             s1 = [r for r in active if r.stage == 1]
             # nobody waiting: the new requests finish in this round too
             fuse = not (pending and pending[0].arrival <= self.ex.now() - t0)
-            self.ex.round(s0, s1, fuse)
+            t_s1 = self.ex.round(s0, s1, fuse)
             now = self.ex.now() - t0
             self.rounds.append((len(s0), len(s1)))
             for r in s1 + (s0 if fuse else []):
-                r.done = now
+                # second-stage results are complete when the round's batch is,
+                # before the new requests' Poisson steps
+                r.done = t_s1 - t0 if (t_s1 is not None and r.stage == 1) else now
                 self.ex.end(r)
                 self._release(r)
                 active.remove(r)
@@ -302,17 +304,32 @@ class GPUExecutor:
         return dict(plan=g.plan, op=_lib.GPW_OP_GRAD, D=r.state["D"], v=r.state["v"], out=out)
 
     def round(self, s0, s1, finish_new=False):
+        """The second stage of s1 as one batch, then the collocation of s0 as
+        another, queued back to back, then the Poisson steps of s0 (and, with
+        finish_new, their second stage).  Returns the time at which the s1
+        results were complete (None without s1), read from a stream event so
+        that the s0 work is not held back by a synchronisation."""
         from . import _lib
-        tasks = [self._second_stage(r) for r in s1]
-        for r in s0:
-            g, _ = self.plans[r.system]
-            tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_RHO, D=r.state["D"], rho=r.state["rho"]))
-        _lib.gpw_eval_batch(tasks)
+        torch = self.torch
+        t_h0 = self.now()
+        ev0 = ev1 = None
+        if s1:
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            _lib.gpw_eval_batch([self._second_stage(r) for r in s1])
+            ev1.record()
+        if s0:
+            tasks = []
+            for r in s0:
+                g, _ = self.plans[r.system]
+                tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_RHO, D=r.state["D"], rho=r.state["rho"]))
+            _lib.gpw_eval_batch(tasks)
         for r in s0:
             self._finish_poisson(r)
         if finish_new and s0:
             _lib.gpw_eval_batch([self._second_stage(r) for r in s0])
-        self.torch.cuda.synchronize(self.dev)
+        torch.cuda.synchronize(self.dev)
+        return t_h0 + ev0.elapsed_time(ev1) * 1e-3 if s1 else None
 
     def single(self, r):
         g, _ = self.plans[r.system]

@@ -12,8 +12,9 @@ from paper_2603_24881_amd.serve import FOCK, GRAD, Request, Scheduler, poisson_t
 
 
 class FakeExecutor:
-    """Virtual clock; a round costs 1 ms plus 1 ms per task, a single request
-    3 ms; records everything the scheduler asks for."""
+    """Virtual clock; a round's eval batch costs 1 ms plus 1 ms per task, then
+    each new request's Poisson step 1 ms (2 ms with its second stage); a single
+    request 3 ms; records everything the scheduler asks for."""
 
     def __init__(self, plan_bytes, req_bytes, budget=None):
         self.t = 0.0
@@ -56,7 +57,10 @@ class FakeExecutor:
     def round(self, s0, s1, finish_new=False):
         assert all(r.stage == 0 for r in s0) and all(r.stage == 1 for r in s1)
         self.log.append(("round", [r.rid for r in s0], [r.rid for r in s1], finish_new))
-        self.t += 1e-3 * (1 + len(s0) * (2 if finish_new else 1) + len(s1))
+        self.t += 1e-3 * (1 + len(s0) + len(s1))        # the batch
+        t_s1 = self.t if s1 else None
+        self.t += 1e-3 * len(s0) * (2 if finish_new else 1)   # Poisson (+ second stage)
+        return t_s1
 
     def single(self, r):
         self.log.append(("single", r.rid))
@@ -106,7 +110,7 @@ def test_lone_request_finishes_in_one_round():
     r = Request(0, FOCK, "a", 0.0)
     s.run([r])
     assert [e for e in ex.log if e[0] == "round"] == [("round", [0], [], True)]
-    assert r.done == pytest.approx(0.003)
+    assert r.done == pytest.approx(0.004)
 
 
 def test_waiting_requests_join_the_next_round():
@@ -119,6 +123,20 @@ def test_waiting_requests_join_the_next_round():
     rounds = [e for e in ex.log if e[0] == "round"]
     assert rounds == [("round", [0, 1], [], False), ("round", [2, 3], [0, 1], False),
                       ("round", [4], [2, 3], True)]
+
+
+def test_second_stage_completes_with_the_batch():
+    """A request in its second stage is complete when the round's batch is,
+    not after the Poisson steps of the requests that joined the round."""
+    ex = FakeExecutor({"a": 10}, {"a": 1})
+    s = _sched(ex, 1000, max_active=2)
+    reqs = [Request(i, FOCK, "a", 0.0) for i in range(3)]
+    s.run(reqs)
+    # round 1: [0, 1] first stage (batch 3 ms + Poisson 2 ms) -> t = 5 ms
+    # round 2: [2] first stage, [0, 1] second (batch 4 ms -> 9 ms; Poisson and
+    # the fused second stage of 2: 2 ms -> 11 ms)
+    assert reqs[0].done == pytest.approx(0.009) and reqs[1].done == pytest.approx(0.009)
+    assert reqs[2].done == pytest.approx(0.011)
 
 
 def test_admission_in_arrival_order_under_budget():
