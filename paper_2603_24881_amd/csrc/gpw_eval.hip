@@ -1172,6 +1172,37 @@ struct PairSmem {
     }
 };
 
+// Matrix element (I, J) of a pair image from its potential moments:
+// sum over the binomial expansion of (x-B)^b around A (Eq. (binomial)) of
+// binom * (A-B)^(b-k) * moment(a + k); ab[d][p] = (A_d - B_d)^p.
+template <int LA, int LB, int I, int J>
+__device__ __forceinline__ double mat_element(const double *mom, const double (*ab)[LB + 1])
+{
+    constexpr int L = LA + LB;
+    constexpr int ax = cart_lx(LA, I), ay = cart_ly(LA, I), az = LA - ax - ay;
+    constexpr int bx = cart_lx(LB, J), by = cart_ly(LB, J), bz = LB - bx - by;
+    double m = 0.0;
+#pragma unroll
+    for (int kx = 0; kx <= bx; ++kx)
+#pragma unroll
+        for (int ky = 0; ky <= by; ++ky)
+#pragma unroll
+            for (int kz = 0; kz <= bz; ++kz)
+                m += (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * ab[0][bx - kx] * ab[1][by - ky] *
+                     ab[2][bz - kz] * mom[tidx(L, ax + kx, ay + ky, az + kz)];
+    return m;
+}
+// Element e of the pair image goes to lane e % 64 (slot e / 64 of m[]); each
+// element is computed under its own lane's mask, so the work is the sum of
+// the elements' terms.
+template <int LA, int LB, int... E>
+__device__ __forceinline__ void mat_elements(std::integer_sequence<int, E...>, const double *mom,
+                                             const double (*ab)[LB + 1], int lane, double *m)
+{
+    constexpr int NB = ncart_c(LB);
+    ((lane == E % 64 ? (void)(m[E / 64] = mat_element<LA, LB, E / NB, E % NB>(mom, ab)) : (void)0), ...);
+}
+
 template <int LA, int LB, typename T>
 __global__ void __launch_bounds__(64)
 k_mat(SegTable<PairSeg> tab)
@@ -1231,29 +1262,93 @@ k_mat(SegTable<PairSeg> tab)
         __syncthreads();
         // element (i, j): the moments of (x-A)^a (x-B)^b with every
         // (x - B_x)^b_x expanded binomially around A (Eq. (binomial))
-        for (int ij = threadIdx.x; ij < NA * NB; ij += 64) {
-            const int i = ij / NB, j = ij - (ij / NB) * NB;
-            const int ax = cart_lx(LA, i), ay = cart_ly(LA, i), az = LA - ax - ay;
-            const int bx = cart_lx(LB, j), by = cart_ly(LB, j), bz = LB - bx - by;
-            double m = 0.0;
-            double px = 1.0;
-            for (int kx = bx; kx >= 0; --kx) {
-                double py = 1.0;
-                for (int ky = by; ky >= 0; --ky) {
-                    double pz = 1.0;
-                    for (int kz = bz; kz >= 0; --kz) {
-                        m += (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * px * py * pz *
-                             mom[tidx(L, ax + kx, ay + ky, az + kz)];
-                        pz *= r.AB[2];
-                    }
-                    py *= r.AB[1];
-                }
-                px *= r.AB[0];
+        double ab[3][LB + 1];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ab[d][0] = 1.0;
+#pragma unroll
+            for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * r.AB[d];
+        }
+        constexpr int NE = NA * NB, NS = (NE + 63) / 64;
+        double m[NS];
+        mat_elements<LA, LB>(std::make_integer_sequence<int, NE>{}, mom, ab, (int)threadIdx.x, m);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int ij = q * 64 + (int)threadIdx.x;
+            if (ij < NE) {
+                const int i = ij / NB, j = ij - (ij / NB) * NB;
+                atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * m[q]);
+                atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * m[q]);
             }
-            atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * m);
-            atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * m);
         }
     }
+}
+
+// Gradient contributions of element (I, J) of a pair image from its potential
+// moments up to degree l_a + l_b + 1: with E = exp(-a |r-A|^2 - b |r-B|^2),
+//   d/dA_d [a_i b_j E] = (2 a (r-A)_d a_i - d_d a_i) b_j E,
+//   d/dB_d [a_i b_j E] = (2 b (r-B)_d b_j - d_d b_j) a_i E,
+// both polynomials in r - A once (r - B) = (r - A) + (A - B) is expanded
+// binomially (Eq. (binomial)); weighted by the symmetrised D_ij into g6.
+template <int LA, int LB, int I, int J>
+__device__ __forceinline__ void grad_element(const double *mom, const double (*ab)[LB + 1], double two_a,
+                                             double two_b, const double *AB, double dij, double *g6)
+{
+    constexpr int L1 = LA + LB + 1;
+    constexpr int a[3] = {cart_lx(LA, I), cart_ly(LA, I), LA - cart_lx(LA, I) - cart_ly(LA, I)};
+    constexpr int b[3] = {cart_lx(LB, J), cart_ly(LB, J), LB - cart_lx(LB, J) - cart_ly(LB, J)};
+    double ga[3] = {0.0, 0.0, 0.0}, gb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kx = 0; kx <= b[0]; ++kx)
+#pragma unroll
+        for (int ky = 0; ky <= b[1]; ++ky)
+#pragma unroll
+            for (int kz = 0; kz <= b[2]; ++kz) {
+                const double c = (double)(binom(b[0], kx) * binom(b[1], ky) * binom(b[2], kz)) * ab[0][b[0] - kx] *
+                                 ab[1][b[1] - ky] * ab[2][b[2] - kz];
+                const int m0 = a[0] + kx, m1 = a[1] + ky, m2 = a[2] + kz;
+                const double M0 = mom[tidx(L1, m0, m1, m2)];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double Md = mom[tidx(L1, m0 + (d == 0), m1 + (d == 1), m2 + (d == 2))];
+                    double da = 0.0;   // d_d (r-A)^a_d
+                    if (a[d] > 0) da = a[d] * mom[tidx(L1, m0 - (d == 0), m1 - (d == 1), m2 - (d == 2))];
+                    ga[d] += c * (two_a * Md - da);
+                    gb[d] += c * two_b * (Md + AB[d] * M0);
+                }
+            }
+    // - a_i d_d b_j(r - B) = - b_d a_i (r - B)^(b - e_d), expanded the same way
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (b[d] == 0) continue;
+        const int c0 = b[0] - (d == 0), c1 = b[1] - (d == 1), c2 = b[2] - (d == 2);
+#pragma unroll
+        for (int kx = 0; kx <= c0; ++kx)
+#pragma unroll
+            for (int ky = 0; ky <= c1; ++ky)
+#pragma unroll
+                for (int kz = 0; kz <= c2; ++kz) {
+                    const double c = (double)(binom(c0, kx) * binom(c1, ky) * binom(c2, kz)) * ab[0][c0 - kx] *
+                                     ab[1][c1 - ky] * ab[2][c2 - kz];
+                    gb[d] -= b[d] * c * mom[tidx(L1, a[0] + kx, a[1] + ky, a[2] + kz)];
+                }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        g6[d] += dij * ga[d];
+        g6[3 + d] += dij * gb[d];
+    }
+}
+template <int LA, int LB, typename T, int... E>
+__device__ __forceinline__ void grad_elements(std::integer_sequence<int, E...>, const double *mom,
+                                              const double (*ab)[LB + 1], double two_a, double two_b,
+                                              const double *AB, const T *Dp, long long n_ao, int lane, double *g6)
+{
+    constexpr int NB = ncart_c(LB);
+    ((lane == E % 64 ? grad_element<LA, LB, E / NB, E % NB>(mom, ab, two_a, two_b, AB,
+                                                            (double)Dp[(E / NB) * n_ao + E % NB], g6)
+                     : (void)0),
+     ...);
 }
 
 template <int LA, int LB, typename T>
@@ -1288,62 +1383,18 @@ k_grad(SegTable<PairSeg> tab)
     double *mom = red + 8 * 65;
     wave_reduce_emit<K, T>(vis.Vm, red, [&](int k, double v) { mom[k] = v; });
     __syncthreads();
-    // lane per element (i, j): with E = exp(-a |r-A|^2 - b |r-B|^2),
-    //   d/dA_d [a_i b_j E] = (2 a (r-A)_d a_i - d_d a_i) b_j E,
-    //   d/dB_d [a_i b_j E] = (2 b (r-B)_d b_j - d_d b_j) a_i E,
-    // both polynomials in r - A once (r - B) = (r - A) + (A - B) is expanded
-    // binomially (Eq. (binomial)); their integrals against v are sums of
-    // moments, weighted by the symmetrised D_ij.
     const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
-    const double two_a = 2.0 * r.aa, two_b = 2.0 * r.ab;
     const double AB[3] = {r.AB[0], r.AB[1], r.AB[2]};
-    auto M = [&](int mx, int my, int mz) { return mom[tidx(L1, mx, my, mz)]; };
-    double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int ij = threadIdx.x; ij < NA * NB; ij += 64) {
-        const int i = ij / NB, j = ij - (ij / NB) * NB;
-        const int a[3] = {cart_lx(LA, i), cart_ly(LA, i), LA - cart_lx(LA, i) - cart_ly(LA, i)};
-        const int b[3] = {cart_lx(LB, j), cart_ly(LB, j), LB - cart_lx(LB, j) - cart_ly(LB, j)};
-        const double dij = (double)Dp[(long long)i * n_ao + j];
-        double ga[3] = {0.0, 0.0, 0.0}, gb[3] = {0.0, 0.0, 0.0};
-        // b_j(r - B) = sum_k c_k (r - A)^k
-        for (int kx = 0; kx <= b[0]; ++kx)
-            for (int ky = 0; ky <= b[1]; ++ky)
-                for (int kz = 0; kz <= b[2]; ++kz) {
-                    double c = (double)(binom(b[0], kx) * binom(b[1], ky) * binom(b[2], kz));
-                    for (int e = kx; e < b[0]; ++e) c *= AB[0];
-                    for (int e = ky; e < b[1]; ++e) c *= AB[1];
-                    for (int e = kz; e < b[2]; ++e) c *= AB[2];
-                    const int m[3] = {a[0] + kx, a[1] + ky, a[2] + kz};
-                    const double M0 = M(m[0], m[1], m[2]);
-                    for (int d = 0; d < 3; ++d) {
-                        const double Md = M(m[0] + (d == 0), m[1] + (d == 1), m[2] + (d == 2));
-                        double da = 0.0;   // d_d (r-A)^a_d
-                        if (a[d] > 0) da = a[d] * M(m[0] - (d == 0), m[1] - (d == 1), m[2] - (d == 2));
-                        ga[d] += c * (two_a * Md - da);
-                        gb[d] += c * two_b * (Md + AB[d] * M0);
-                    }
-                }
-        // - a_i d_d b_j(r - B) = - b_d a_i (r - B)^(b - e_d), expanded the same way
-        for (int d = 0; d < 3; ++d) {
-            if (b[d] == 0) continue;
-            int bb[3] = {b[0], b[1], b[2]};
-            bb[d] -= 1;
-            for (int kx = 0; kx <= bb[0]; ++kx)
-                for (int ky = 0; ky <= bb[1]; ++ky)
-                    for (int kz = 0; kz <= bb[2]; ++kz) {
-                        double c = (double)(binom(bb[0], kx) * binom(bb[1], ky) * binom(bb[2], kz));
-                        for (int e = kx; e < bb[0]; ++e) c *= AB[0];
-                        for (int e = ky; e < bb[1]; ++e) c *= AB[1];
-                        for (int e = kz; e < bb[2]; ++e) c *= AB[2];
-                        gb[d] -= b[d] * c * M(a[0] + kx, a[1] + ky, a[2] + kz);
-                    }
-        }
+    double ab[3][LB + 1];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            g6[d] += dij * ga[d];
-            g6[3 + d] += dij * gb[d];
-        }
+    for (int d = 0; d < 3; ++d) {
+        ab[d][0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * AB[d];
     }
+    double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    grad_elements<LA, LB, T>(std::make_integer_sequence<int, NA * NB>{}, mom, ab, 2.0 * r.aa, 2.0 * r.ab, AB, Dp,
+                             n_ao, (int)threadIdx.x, g6);
     const double scale = G.w * r.Kw;
     __syncthreads();   // every read of the moments is done
     wave_reduce_emit<6, double>(g6, red, [&](int k, double v) {
