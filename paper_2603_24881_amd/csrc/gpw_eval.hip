@@ -741,7 +741,7 @@ template <> struct RhoSplit<2, 1> {
     static constexpr bool stage = true, two = false;
 };
 template <> struct RhoSplit<2, 2> {
-    static constexpr int npass = 2, wpe = 2, wpe2 = 2;
+    static constexpr int npass = 1, wpe = 1, wpe2 = 2;
     static constexpr bool stage = false, two = false;
 };
 template <> struct RhoSplit<3, 0> {
@@ -749,11 +749,11 @@ template <> struct RhoSplit<3, 0> {
     static constexpr bool stage = false, two = false;
 };
 template <> struct RhoSplit<3, 1> {
-    static constexpr int npass = 2, wpe = 1, wpe2 = 1;
+    static constexpr int npass = 1, wpe = 1, wpe2 = 1;
     static constexpr bool stage = false, two = false;
 };
 template <> struct RhoSplit<3, 2> {
-    static constexpr int npass = 2, wpe = 1, wpe2 = 1;
+    static constexpr int npass = 1, wpe = 1, wpe2 = 1;
     static constexpr bool stage = false, two = false;
 };
 template <> struct RhoSplit<3, 3> {
