@@ -742,7 +742,7 @@ template <> struct RhoSplit<2, 1> {
 };
 template <> struct RhoSplit<2, 2> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 2;
-    static constexpr bool stage = false, two = false;
+    static constexpr bool stage = true, two = false;
 };
 template <> struct RhoSplit<3, 0> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 1;
