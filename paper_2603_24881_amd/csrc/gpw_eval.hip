@@ -782,15 +782,16 @@ __device__ __forceinline__ double uni(double v)
 
 // 1-D point tables of a pair image, at point 4 e + t of an axis (point t of
 // block list entry e): the envelope factor exp(-alpha_p (x - P)^2) and the
-// offsets x - A (and, along z, x - B).
+// offset x - A; along z two more values: for the direct form z - B and 0,
+// for the moment form (z - A)^2 and (z - A)^3.
 template <typename T> struct alignas(2 * sizeof(T)) PtXY { T e, a; };
-template <typename T> struct alignas(4 * sizeof(T)) PtZ { T e, a, b, pad; };
+template <typename T> struct alignas(4 * sizeof(T)) PtZ { T e, a, b, c; };
 
 // LDS set-up of one pair image: per axis, the list of the blocks (with fold
 // shifts) its bounding box meets, one entry per lane, and the point tables of
 // the entries, so that the points of a run of consecutive entries sit at
 // consecutive table positions.  emax bounds every list (the plan's longest).
-template <typename T>
+template <bool MOM, typename T>
 __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G, PtXY<T> *txy, PtZ<T> *tz,
                                            AxisBlock *bl, int emax, int *cnt)
 {
@@ -829,7 +830,10 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             if (d < 2) {
                 txy[d * 4 * emax + i] = PtXY<T>{(T)e, (T)a};
             } else {
-                tz[i] = PtZ<T>{(T)e, (T)a, (T)(a + r.AB[2]), T(0)};
+                if (MOM)
+                    tz[i] = PtZ<T>{(T)e, (T)a, (T)(a * a), (T)(a * a * a)};
+                else
+                    tz[i] = PtZ<T>{(T)e, (T)a, (T)(a + r.AB[2]), T(0)};
             }
         }
     }
@@ -1095,16 +1099,22 @@ struct TensorVisit {
         ey = Y.e;
         exy = ex * ey;
     }
+    // Z.b, Z.c hold (z - A_z)^2 and (z - A_z)^3
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T E = exy * Z.e;
         const T f = (E >= ER) ? v * Z.e : T(0);
         W[0] += f;
-        T p = f;
+        if constexpr (L >= 1) W[1] += f * Z.a;
+        if constexpr (L >= 2) W[2] += f * Z.b;
+        if constexpr (L >= 3) W[3] += f * Z.c;
+        if constexpr (L >= 4) {
+            T p = Z.c;
 #pragma unroll
-        for (int lz = 1; lz <= L; ++lz) {
-            p *= Z.a;
-            W[lz] += p;
+            for (int lz = 4; lz <= L; ++lz) {
+                p *= Z.a;
+                W[lz] += f * p;
+            }
         }
     }
     __device__ __forceinline__ void done()
@@ -1222,7 +1232,7 @@ k_mat(SegTable<PairSeg> tab)
     const double *__restrict__ Vb = sg.Vb;
     PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
-    pair_setup<T>(r, G, txy, tz, bl, emax, cnt);
+    pair_setup<mat_tensor(LA, LB), T>(r, G, txy, tz, bl, emax, cnt);
     __syncthreads();
     const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
     __syncthreads();
@@ -1371,7 +1381,7 @@ k_grad(SegTable<PairSeg> tab)
     const double *__restrict__ Vb = sg.Vb;
     PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
     const PairRec &r = sg.pairs[item];
-    pair_setup<T>(r, G, txy, tz, bl, emax, cnt);
+    pair_setup<true, T>(r, G, txy, tz, bl, emax, cnt);
     __syncthreads();
     const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
     __syncthreads();
