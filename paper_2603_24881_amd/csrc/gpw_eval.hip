@@ -529,7 +529,9 @@ __device__ __forceinline__ void rho_points_direct(const T *Dk, double xa0, doubl
                 }
                 acc[ix * 16 + ty * 4 + tz] += E * sum;
             }
-            __builtin_amdgcn_sched_barrier(0);
+            // bounds the live monomials of the widest classes; the others
+            // schedule better across columns
+            if constexpr (LA + LB >= 5) __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
