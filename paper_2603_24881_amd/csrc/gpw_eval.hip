@@ -3,19 +3,24 @@
 // rho  - grid-block major, after Alg. 1 of the paper, mapped to CDNA: one
 //        wave64 owns one 4x4x4 block of one level and walks the block's list
 //        of pair images in batches of 64, lane = pair image.  Each lane holds
-//        its image's geometry and Kw-scaled D sub-block in registers,
-//        evaluates the separable envelope of Sec. III.A (Eqs. (gx), (gab),
-//        (exp_rr)) on the block's 64 points and the polynomial prefactor
-//        directly per point, and accumulates the 64 point values in
+//        its image's geometry and coefficients in registers, evaluates the
+//        separable envelope of Sec. III.A (Eqs. (gx), (gab), (exp_rr)) on the
+//        block's 64 points and the polynomial prefactor per point, either
+//        through the coefficient tensor of Eq. (rho1) by Horner's rule one
+//        axis at a time (d and f classes) or directly from the Kw-scaled D
+//        sub-block (s and p classes), and accumulates the 64 point values in
 //        registers; one LDS transpose-reduction per block sums the lanes and
 //        each point is written once.
 // mat  - pair major: one wave per pair image walks the 4x4x4 blocks its
 //        truncation sphere meets (the same block set as rho), lane = point,
-//        accumulating the n_a x n_b local integrals (Alg. 2's F^local) in
-//        registers over all blocks, then one wave reduction and one atomic add
-//        per matrix element per pair image instead of one per (pair, block).
-// grad - same traversal as mat with the six derivative accumulators of
-//        Alg. 3 (d/dA and d/dB contracted with D and v on the fly).
+//        accumulating over all blocks either the potential moments of the
+//        monomials of r - A one axis at a time (the integration analogue of
+//        Eq. (rho1), l_a + l_b >= 2) or the n_a x n_b local integrals (Alg. 2's
+//        F^local), then one wave reduction and one atomic add per matrix
+//        element per pair image instead of one per (pair, block).
+// grad - same traversal as mat, moments one degree higher, from which the
+//        d/dA and d/dB contributions of Alg. 3 are formed and contracted
+//        with D once per pair image.
 // Every kernel is templated on (l_a, l_b) and on the per-point arithmetic
 // type (double, or float for the FP32 variant; exponents, centres and the
 // cross-level/matrix accumulation stay in double).
@@ -557,7 +562,7 @@ __device__ __forceinline__ void rho_lane_points(const T *C, double xa0, double y
 // batches ahead; geometry and D one batch ahead, straight into LDS) are issued
 // before the current batch is computed, so their latency hides behind the
 // arithmetic.  NPASS splits the 64 points to bound the accumulator registers.
-template <int LA, int LB, int NPASS, int WPE, bool STG, typename T>
+template <int LA, int LB, int NPASS, int WPE, bool STG, bool PREF, typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_rho(SegTable<RhoSeg> tab)
 {
@@ -593,9 +598,12 @@ k_rho(SegTable<RhoSeg> tab)
         // the start of each batch)
         int2 en1 = inc[s0 + lane < s1 ? s0 + lane : s1 - 1];
         int2 en2 = inc[s0 + 64 + lane < s1 ? s0 + 64 + lane : s1 - 1];
+        Lane nxt;   // PREF: the next batch's state, loaded while this one is computed
         if constexpr (STG) {
             asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
             Lane::stage(rr, Dpk, en1.x - p0, lds);
+        } else if constexpr (PREF) {
+            nxt.load_global(rr, Dpk, en1.x - p0);
         }
         for (long long s = s0; s < s1; s += 64) {
             const bool act = s + lane < s1;
@@ -606,6 +614,9 @@ k_rho(SegTable<RhoSeg> tab)
                 cur.load(lds, lane);
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); // read before the area is refilled
                 if (s + 64 < s1) Lane::stage(rr, Dpk, en2.x - p0, lds);
+            } else if constexpr (PREF) {
+                cur = nxt;
+                if (s + 64 < s1) nxt.load_global(rr, Dpk, en2.x - p0);
             } else {
                 cur.load_global(rr, Dpk, en.x - p0);
             }
@@ -724,43 +735,44 @@ k_rho2(SegTable<RhoSeg> tab)
 }
 
 // per class: points per pass (NPASS), waves per SIMD, whether the next batch
-// is staged in LDS, and whether two waves share a block (k_rho2, at WPE2
-// workgroups per SIMD) (chosen by measurement on the 256-water system)
+// is staged in LDS or else (pref) loaded into registers one batch ahead, and
+// whether two waves share a block (k_rho2, at WPE2 workgroups per SIMD)
+// (chosen by measurement on the 256-water system)
 template <int LA, int LB> struct RhoSplit {
     static constexpr int npass = 1, wpe = 2, wpe2 = 1;
-    static constexpr bool stage = false, two = false;
+    static constexpr bool stage = false, two = false, pref = true;
 };
 template <> struct RhoSplit<1, 1> {
     static constexpr int npass = 1, wpe = 2, wpe2 = 2;
-    static constexpr bool stage = true, two = false;
+    static constexpr bool stage = true, two = false, pref = false;
 };
 template <> struct RhoSplit<2, 0> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 2;
-    static constexpr bool stage = true, two = true;
+    static constexpr bool stage = true, two = true, pref = false;
 };
 template <> struct RhoSplit<2, 1> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 2;
-    static constexpr bool stage = true, two = false;
+    static constexpr bool stage = true, two = false, pref = false;
 };
 template <> struct RhoSplit<2, 2> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 2;
-    static constexpr bool stage = true, two = false;
+    static constexpr bool stage = true, two = false, pref = false;
 };
 template <> struct RhoSplit<3, 0> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 1;
-    static constexpr bool stage = false, two = false;
+    static constexpr bool stage = false, two = false, pref = false;
 };
 template <> struct RhoSplit<3, 1> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 1;
-    static constexpr bool stage = false, two = false;
+    static constexpr bool stage = false, two = false, pref = false;
 };
 template <> struct RhoSplit<3, 2> {
     static constexpr int npass = 1, wpe = 1, wpe2 = 1;
-    static constexpr bool stage = false, two = false;
+    static constexpr bool stage = false, two = false, pref = false;
 };
 template <> struct RhoSplit<3, 3> {
     static constexpr int npass = 4, wpe = 1, wpe2 = 1;
-    static constexpr bool stage = false, two = false;
+    static constexpr bool stage = false, two = false, pref = false;
 };
 
 // ----------------------------------------------- pair-major traversal (mat, grad)
@@ -1617,8 +1629,8 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
                 if constexpr (RS::two)
                     hipLaunchKernelGGL((k_rho2<LA, LB, RS::wpe2, T>), dim3(g), dim3(128), 0, st, tb);
                 else
-                    hipLaunchKernelGGL((k_rho<LA, LB, RS::npass, RS::wpe, RS::stage, T>), dim3(g), dim3(64), 0, st,
-                                       tb);
+                    hipLaunchKernelGGL((k_rho<LA, LB, RS::npass, RS::wpe, RS::stage, RS::pref, T>), dim3(g), dim3(64),
+                                       0, st, tb);
             }, true);
             mats.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
                 hipLaunchKernelGGL((k_mat<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
