@@ -198,8 +198,8 @@ def serving(n, rates, budget_gb):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
-                                   "(the path shards by grid blocks, see DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus above 1 is not supported (the path would shard by "
+                                   "grid blocks, with one all-reduce of M per evaluation)"}))
         sys.exit(2)
     import torch
     from paper_2603_24881_amd import synth

@@ -184,7 +184,7 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
     if (guard.err != hipSuccess) { free_plan(pl); return hip_fail(guard.err, "gpw_plan: hipSetDevice"); }
     {
         // The eval calls take their scratch from the device's default stream-ordered
-        // pool; keep freed blocks in the pool instead of returning them to the driver
+        // pool; keep freed blocks in the pool instead of returning them to the HIP runtime
         // at every synchronisation, so that repeated evaluations do not remap memory.
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, pl->device) == hipSuccess) {

@@ -132,8 +132,8 @@ def test_second_stage_completes_with_the_batch():
     s = _sched(ex, 1000, max_active=2)
     reqs = [Request(i, FOCK, "a", 0.0) for i in range(3)]
     s.run(reqs)
-    # round 1: [0, 1] first stage (batch 3 ms + Poisson 2 ms) -> t = 5 ms
-    # round 2: [2] first stage, [0, 1] second (batch 4 ms -> 9 ms; Poisson and
+    # first round: [0, 1] first stage (batch 3 ms + Poisson 2 ms) -> t = 5 ms
+    # second round: [2] first stage, [0, 1] second (batch 4 ms -> 9 ms; Poisson and
     # the fused second stage of 2: 2 ms -> 11 ms)
     assert reqs[0].done == pytest.approx(0.009) and reqs[1].done == pytest.approx(0.009)
     assert reqs[2].done == pytest.approx(0.011)
