@@ -137,3 +137,36 @@ def test_fp32_variant_error_is_bounded():
     errs = [rel_err(a, b) for a, b in zip(rho_g, rho_o)] + [rel_err(M_g, M_o), rel_err(g_g, g_o)]
     log(f"  fp32 rel errs {['%.1e' % e for e in errs]}")
     assert max(errs) < 1e-4
+
+
+def test_flop_model_follows_its_definition():
+    """The plan's work counts, per (l_a, l_b) class over all ten classes: the
+    counting convention (direct evaluation, 64 points per block incidence),
+    the kernels' arithmetic (coefficient tensor for the rho d and f classes
+    except (f|s), (f|f); moments for mat with l_a + l_b >= 2) and the
+    in-sphere count below the block count."""
+    from math import comb
+    from paper_2603_24881_amd.gpw import GPW
+    s = tiny.tiny_system(mesh=((20, 24, 28),), tau=1e-10)
+    g = GPW(s)
+    info = g.info
+    g.close()
+    conv = exec_rho = exec_mat = 0.0
+    for la in range(4):
+        for lb in range(la + 1):
+            c = la * (la + 1) // 2 + lb
+            inc = info["n_incidences_class"][c]
+            na, nb, L = (la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2, la + lb
+            f1 = 2 * na * nb + 2 * (na + nb) + 4
+            conv += 64.0 * f1 * inc
+            tensor_rho = la == 2 or (la == 3 and 1 <= lb <= 2)
+            exec_rho += (8 * comb(L + 2, 3) + 32 * comb(L + 1, 2) + 16 + 64 * (2 * L + 3) if tensor_rho
+                         else 64 * f1) * inc
+            exec_mat += 64.0 * ((2 * L + 3) if L >= 2 else f1) * inc
+    assert all(info["n_incidences_class"][c] > 0 for c in range(10))
+    assert info["flops_rho_block"] == pytest.approx(conv, rel=1e-12)
+    assert info["flops_mat_block"] == pytest.approx(conv, rel=1e-12)
+    assert info["flops_rho_exec"] == pytest.approx(exec_rho, rel=1e-12)
+    assert info["flops_mat_exec"] == pytest.approx(exec_mat, rel=1e-12)
+    assert 0 < info["flops_rho_sphere"] <= info["flops_rho_block"]
+    assert info["flops_rho_exec"] < info["flops_rho_block"]
