@@ -311,6 +311,10 @@ class GPUExecutor:
         that the s0 work is not held back by a synchronisation."""
         from . import _lib
         torch = self.torch
+        if finish_new and len(s0) == 1 and not s1:
+            # a lone request: the plain calls, as the one-at-a-time server makes them
+            self.single(s0[0])
+            return None
         t_h0 = self.now()
         ev0 = ev1 = None
         if s1:
