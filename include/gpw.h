@@ -141,6 +141,10 @@ typedef struct {
     double flops_rho_exec, flops_mat_exec;
     long long device_bytes;                   /* device memory held by the plan */
     int max_box_width;                        /* widest bounding box (points per axis) */
+    long long scratch_bytes[3];               /* device scratch of one evaluation, indexed by the op
+                                                 value GPW_OP_RHO, _MAT, _GRAD; taken from the pool
+                                                 for the duration of the call (a batch takes the sum
+                                                 over its tasks) */
 } gpw_plan_info;
 
 /* Build a plan: screen primitive pair images, assign levels, compute their

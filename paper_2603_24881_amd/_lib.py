@@ -84,6 +84,7 @@ class gpw_plan_info(C.Structure):
         ("flops_mat_exec", C.c_double),
         ("device_bytes", C.c_longlong),
         ("max_box_width", C.c_int),
+        ("scratch_bytes", C.c_longlong * 3),
     ]
 
 
@@ -149,11 +150,33 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def _dev_ptr(t, what):
+def _dev_ptr(t, what, numel=None, device=None):
+    """Device address of a contiguous float64 tensor, after checking its size and
+    device against what the library will read or write through it."""
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise TypeError(f"{what}: expected a contiguous float64 device tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, the plan needs {numel}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what}: on device {t.device.index}, the plan lives on device {device}")
     return t.data_ptr()
+
+
+def _level_ptrs(plan, arrs, what):
+    """Host array of the plan's nlevels level-grid pointers (sizes checked)."""
+    if arrs is None or len(arrs) != plan.nlevels:
+        raise ValueError(f"{what}: expected one grid per level ({plan.nlevels}), got "
+                         f"{None if arrs is None else len(arrs)}")
+    return _ptr_array([_dev_ptr(a, f"{what}[{l}]", plan.n_grid[l], plan.device) for l, a in enumerate(arrs)])
+
+
+def _mat_ptr(plan, t, what):
+    return _dev_ptr(t, what, plan.n_ao * plan.n_ao, plan.device)
+
+
+def _grad_ptr(plan, t, what):
+    return _dev_ptr(t, what, plan.natm * 3, plan.device)
 
 
 class PlanHandle:
@@ -209,6 +232,10 @@ class PlanHandle:
         self.handle = h.value
         self.device = int(device)
         self.info = self.query()
+        self.nlevels = self.info["nlevels"]
+        self.n_grid = [int(x) for x in self.info["n_grid"]]
+        self.n_ao = int(self.info["n_ao"])
+        self.natm = int(self.info["natm"])
 
     def query(self) -> dict:
         info = gpw_plan_info()
@@ -230,6 +257,7 @@ class PlanHandle:
             "flops_grad_block": info.flops_grad_block, "flops_grad_sphere": info.flops_grad_sphere,
             "flops_rho_exec": info.flops_rho_exec, "flops_mat_exec": info.flops_mat_exec,
             "device_bytes": info.device_bytes, "max_box_width": info.max_box_width,
+            "scratch_bytes": list(info.scratch_bytes),
         }
 
     def close(self):
@@ -257,18 +285,18 @@ def gpw_plan_query(plan: PlanHandle) -> dict:
 
 
 def gpw_eval_rho(plan: PlanHandle, D, rho, stream=None):
-    arr = _ptr_array([_dev_ptr(r, "rho[l]") for r in rho])
-    _check(load().gpw_eval_rho(plan.handle, _dev_ptr(D, "D"), arr, _stream_handle(stream)))
+    arr = _level_ptrs(plan, rho, "rho")
+    _check(load().gpw_eval_rho(plan.handle, _mat_ptr(plan, D, "D"), arr, _stream_handle(stream)))
 
 
 def gpw_eval_mat(plan: PlanHandle, v, M, stream=None):
-    arr = _ptr_array([_dev_ptr(x, "v[l]") for x in v])
-    _check(load().gpw_eval_mat(plan.handle, arr, _dev_ptr(M, "M"), _stream_handle(stream)))
+    arr = _level_ptrs(plan, v, "v")
+    _check(load().gpw_eval_mat(plan.handle, arr, _mat_ptr(plan, M, "M"), _stream_handle(stream)))
 
 
 def gpw_eval_grad(plan: PlanHandle, D, v, grad, stream=None):
-    arr = _ptr_array([_dev_ptr(x, "v[l]") for x in v])
-    _check(load().gpw_eval_grad(plan.handle, _dev_ptr(D, "D"), arr, _dev_ptr(grad, "grad"),
+    arr = _level_ptrs(plan, v, "v")
+    _check(load().gpw_eval_grad(plan.handle, _mat_ptr(plan, D, "D"), arr, _grad_ptr(plan, grad, "grad"),
                                 _stream_handle(stream)))
 
 
@@ -278,18 +306,25 @@ def gpw_eval_batch(tasks, stream=None):
     arr = (gpw_task * max(1, n))()
     keep = []
     for i, t in enumerate(tasks):
-        arr[i].plan = t["plan"].handle
-        arr[i].op = int(t["op"])
-        arr[i].D = _dev_ptr(t["D"], "D") if t.get("D") is not None else None
-        if t.get("v") is not None:
-            va = _ptr_array([_dev_ptr(x, "v[l]") for x in t["v"]])
+        plan, op = t["plan"], int(t["op"])
+        arr[i].plan = plan.handle
+        arr[i].op = op
+        if op not in (GPW_OP_RHO, GPW_OP_MAT, GPW_OP_GRAD):
+            raise ValueError(f"task {i}: unknown op {op}")
+        if op in (GPW_OP_RHO, GPW_OP_GRAD):
+            arr[i].D = _mat_ptr(plan, t.get("D"), f"task {i} D")
+        if op in (GPW_OP_MAT, GPW_OP_GRAD):
+            va = _level_ptrs(plan, t.get("v"), f"task {i} v")
             keep.append(va)
             arr[i].v = C.cast(va, C.c_void_p)
-        if t.get("rho") is not None:
-            ra = _ptr_array([_dev_ptr(x, "rho[l]") for x in t["rho"]])
+        if op == GPW_OP_RHO:
+            ra = _level_ptrs(plan, t.get("rho"), f"task {i} rho")
             keep.append(ra)
             arr[i].rho = C.cast(ra, C.c_void_p)
-        arr[i].out = _dev_ptr(t["out"], "out") if t.get("out") is not None else None
+        elif op == GPW_OP_MAT:
+            arr[i].out = _mat_ptr(plan, t.get("out"), f"task {i} M")
+        else:
+            arr[i].out = _grad_ptr(plan, t.get("out"), f"task {i} grad")
     _check(load().gpw_eval_batch(arr, n, _stream_handle(stream)))
 
 

@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpw.so")
-SOURCES = ["gpw_api.hip", "gpw_partition.hip", "gpw_eval.hip", "gpw_batch.hip"]
+SOURCES = ["gpw_api.hip", "gpw_partition.hip", "gpw_eval.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link libgpw.so next to this file."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = list(SOURCES)
     with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir), srcs))
     tmp = LIB + f".tmp{os.getpid()}"

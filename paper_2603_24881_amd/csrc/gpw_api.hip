@@ -7,7 +7,8 @@
 #include "gpw_internal.h"
 
 namespace gpw {
-hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t st, std::string &err);
+hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t st, std::string &err,
+                           bool &unsupported);
 }  // namespace gpw
 
 using namespace gpw;
@@ -55,7 +56,8 @@ struct DeviceGuard {
 void free_plan(gpw_plan_s *pl)
 {
     if (!pl) return;
-    for (void *p : pl->allocations) (void)hipFree(p);
+    for (void *p : pl->allocations)
+        if (p) (void)hipFree(p);
     delete pl;
 }
 
@@ -221,14 +223,15 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
         in.pc.geom[l] = pl->geom[l];
     }
     std::string err;
-    e = build_partition(pl, in, st, err);
+    bool unsupported = false;
+    e = build_partition(pl, in, st, err, unsupported);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
     if (e != hipSuccess) {
         free_plan(pl);
-        const gpw_status st_code = e == hipErrorOutOfMemory   ? GPW_ENOMEM
-                                   : e == hipErrorInvalidValue ? GPW_EUNSUPPORTED
-                                                               : GPW_EDEVICE;
+        const gpw_status st_code = unsupported ? GPW_EUNSUPPORTED
+                                   : e == hipErrorOutOfMemory ? GPW_ENOMEM
+                                                              : GPW_EDEVICE;
         return fail(st_code, "gpw_plan: " + err);
     }
     {
@@ -261,6 +264,7 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
                      (long long)sizeof(long long) * (pl->cnt_base[kMaxGroups] + 2) +
                      (long long)sizeof(int) * pl->blk_off[kMaxGroups] +
                      (long long)n_ps * (3 * sizeof(int) + 2 * sizeof(double)) + 24LL * pl->natm;
+    for (int op = GPW_OP_RHO; op <= GPW_OP_GRAD; ++op) I.scratch_bytes[op] = (long long)gpw::eval_scratch_bytes(pl, op);
     *out = pl;
     return GPW_OK;
 }

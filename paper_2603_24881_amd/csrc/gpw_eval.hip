@@ -1499,6 +1499,42 @@ struct TaskScratch {
     long long voff[kMaxLevels];          // block-grid offsets of the levels (doubles)
 };
 
+// Layout of one task's scratch (byte offsets from base) and its size.
+template <typename T>
+static size_t task_scratch(const gpw_plan_s *pl, int op, size_t base, TaskScratch &x)
+{
+    size_t bytes = base;
+    if (op == GPW_OP_RHO) {
+        x.dbase[0] = 0;
+        for (int g = 0; g < kMaxGroups; ++g) {
+            const int c = g % kNCls;
+            x.dbase[g + 1] = x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) *
+                                              cstride<T>(rho_ncoef(cls_la(c), cls_lb(c)));
+        }
+        x.dpk = bytes;
+        bytes += align256(sizeof(T) * (size_t)x.dbase[kMaxGroups]);
+    } else {
+        long long tot = 0;
+        for (int l = 0; l < pl->nlevels; ++l) {
+            x.voff[l] = tot;
+            tot += block_copy_blocks(pl, l) * 64;
+        }
+        x.vb = bytes;
+        bytes += align256(sizeof(double) * (size_t)(tot + 64 * kBlockCopyTail));
+        if (op == GPW_OP_GRAD) {
+            x.ds = bytes;
+            bytes += align256(sizeof(T) * (size_t)pl->n_ao * pl->n_ao);
+        }
+    }
+    return bytes - base;
+}
+
+size_t eval_scratch_bytes(const gpw_plan_s *pl, int op)
+{
+    TaskScratch x;
+    return pl->precision == GPW_FP32 ? task_scratch<float>(pl, op, 0, x) : task_scratch<double>(pl, op, 0, x);
+}
+
 template <typename T>
 static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
 {
@@ -1506,32 +1542,8 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
     size_t bytes = 0;
     int emax_all = 1;
     for (int i = 0; i < n; ++i) {
-        const TaskRef &t = tasks[i];
-        const gpw_plan_s *pl = t.pl;
-        TaskScratch &x = ts[i];
-        if (t.op == GPW_OP_RHO) {
-            x.dbase[0] = 0;
-            for (int g = 0; g < kMaxGroups; ++g) {
-                const int c = g % kNCls;
-                x.dbase[g + 1] = x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) *
-                                                  cstride<T>(rho_ncoef(cls_la(c), cls_lb(c)));
-            }
-            x.dpk = bytes;
-            bytes += align256(sizeof(T) * (size_t)x.dbase[kMaxGroups]);
-        } else {
-            long long tot = 0;
-            for (int l = 0; l < pl->nlevels; ++l) {
-                x.voff[l] = tot;
-                tot += block_copy_blocks(pl, l) * 64;
-            }
-            x.vb = bytes;
-            bytes += align256(sizeof(double) * (size_t)(tot + 64 * kBlockCopyTail));
-            emax_all = std::max(emax_all, pl->max_axis_blocks);
-            if (t.op == GPW_OP_GRAD) {
-                x.ds = bytes;
-                bytes += align256(sizeof(T) * (size_t)pl->n_ao * pl->n_ao);
-            }
-        }
+        bytes += task_scratch<T>(tasks[i].pl, tasks[i].op, bytes, ts[i]);
+        if (tasks[i].op != GPW_OP_RHO) emax_all = std::max(emax_all, tasks[i].pl->max_axis_blocks);
     }
     unsigned char *scr = nullptr;
     hipError_t e = hipMallocAsync((void **)&scr, bytes > 0 ? bytes : 256, st);

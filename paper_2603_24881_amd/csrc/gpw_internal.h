@@ -304,6 +304,8 @@ struct TaskRef {
     double *out;
 };
 hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st);
+// Device scratch one evaluation of op (gpw_op) takes from the stream-ordered pool.
+size_t eval_scratch_bytes(const gpw_plan_s *pl, int op);
 // LDS bytes a workgroup of the pair-major kernels (mat, grad) needs for a plan
 // whose longest per-axis block list of a pair image has emax entries.
 size_t pair_kernel_lds_bytes(int emax, int precision);

@@ -368,22 +368,21 @@ static hipError_t exclusive_scan(const TIn *in, long long n, long long *out, hip
     const long long nchunk = (n + kScanChunk - 1) / kScanChunk;
     long long *partial = nullptr, *chunk_off = nullptr;
     hipError_t e = hipMallocAsync((void **)&partial, sizeof(long long) * nchunk, st);
-    if (e != hipSuccess) return e;
-    e = hipMallocAsync((void **)&chunk_off, sizeof(long long) * (nchunk + 1), st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3((unsigned)nchunk), dim3(256), 0, st, in, n, partial);
-    if (nchunk == 1) {
-        long long zero = 0;
-        e = hipMemcpyAsync(chunk_off, &zero, sizeof(zero), hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return e;
-    } else {
-        e = exclusive_scan<long long>(partial, nchunk, chunk_off, st);
-        if (e != hipSuccess) return e;
+    if (e == hipSuccess) e = hipMallocAsync((void **)&chunk_off, sizeof(long long) * (nchunk + 1), st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_scan_reduce<TIn>, dim3((unsigned)nchunk), dim3(256), 0, st, in, n, partial);
+        if (nchunk == 1) {
+            long long zero = 0;
+            e = hipMemcpyAsync(chunk_off, &zero, sizeof(zero), hipMemcpyHostToDevice, st);
+        } else {
+            e = exclusive_scan<long long>(partial, nchunk, chunk_off, st);
+        }
     }
-    hipLaunchKernelGGL(k_scan_apply<TIn>, dim3((unsigned)nchunk), dim3(256), 0, st, in, n, chunk_off, out);
-    (void)hipFreeAsync(partial, st);
-    (void)hipFreeAsync(chunk_off, st);
-    return hipGetLastError();
+    if (e == hipSuccess)
+        hipLaunchKernelGGL(k_scan_apply<TIn>, dim3((unsigned)nchunk), dim3(256), 0, st, in, n, chunk_off, out);
+    if (partial) (void)hipFreeAsync(partial, st);
+    if (chunk_off) (void)hipFreeAsync(chunk_off, st);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 __global__ void k_flags(const unsigned *cnt, long long n, unsigned *flags)
@@ -407,25 +406,64 @@ __global__ void k_compact_blocks(const unsigned *cnt, long long n, const long lo
 
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Device temporaries of one plan construction, freed on every exit.
+struct Temps {
+    std::vector<void *> p;
+    template <typename T>
+    hipError_t alloc(T **ptr, size_t bytes)
+    {
+        *ptr = nullptr;
+        hipError_t e = hipMalloc((void **)ptr, bytes);
+        if (e == hipSuccess) p.push_back((void *)*ptr);
+        return e;
+    }
+    void release(void *q)
+    {
+        for (auto &x : p)
+            if (x == q) {
+                (void)hipFree(x);
+                x = nullptr;
+            }
+    }
+    ~Temps()
+    {
+        for (void *x : p)
+            if (x) (void)hipFree(x);
+    }
+};
+
 // Runs the partitioner on the plan's device; fills pairs, incidences, block
-// lists and work statistics.  Returns a HIP error code.
-hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t st, std::string &err)
+// lists and work statistics.  Returns a HIP error code; a plan the kernels
+// cannot evaluate (a truncation sphere too wide) sets unsupported and returns
+// hipErrorInvalidValue.  Buffers the plan keeps are registered in its
+// allocation list as soon as they exist, so free_plan releases them on any
+// error; the temporaries are released here on every path.
+hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t st, std::string &err,
+                           bool &unsupported)
 {
     hipError_t e;
+    unsupported = false;
+    Temps tmp;
 #define PCHK(x)                                                                                 \
     do {                                                                                        \
         e = (x);                                                                                \
         if (e != hipSuccess) { err = std::string(#x) + ": " + hipGetErrorString(e); return e; } \
     } while (0)
+    auto own = [&](auto **ptr, size_t bytes) -> hipError_t {
+        *ptr = nullptr;
+        hipError_t r = hipMalloc((void **)ptr, bytes);
+        if (r == hipSuccess) pl->allocations.push_back((void *)*ptr);
+        return r;
+    };
     const int ngroups = pl->nlevels * kNCls;
     unsigned long long *d_gcnt = nullptr, *d_gcur = nullptr;
     long long *d_goff = nullptr;
     int *d_err = nullptr;
-    PCHK(hipMalloc(&d_err, sizeof(int)));
+    PCHK(tmp.alloc(&d_err, sizeof(int)));
     PCHK(hipMemsetAsync(d_err, 0, sizeof(int), st));
-    PCHK(hipMalloc(&d_gcnt, sizeof(unsigned long long) * kMaxGroups));
-    PCHK(hipMalloc(&d_gcur, sizeof(unsigned long long) * kMaxGroups));
-    PCHK(hipMalloc(&d_goff, sizeof(long long) * (kMaxGroups + 1)));
+    PCHK(tmp.alloc(&d_gcnt, sizeof(unsigned long long) * kMaxGroups));
+    PCHK(tmp.alloc(&d_gcur, sizeof(unsigned long long) * kMaxGroups));
+    PCHK(tmp.alloc(&d_goff, sizeof(long long) * (kMaxGroups + 1)));
     PCHK(hipMemsetAsync(d_gcnt, 0, sizeof(unsigned long long) * kMaxGroups, st));
     PCHK(hipMemsetAsync(d_gcur, 0, sizeof(unsigned long long) * kMaxGroups, st));
 
@@ -440,8 +478,7 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     for (int g = 0; g < kMaxGroups; ++g) pl->group_off[g + 1] = pl->group_off[g] + (g < ngroups ? (long long)gcnt[g] : 0);
     pl->n_pairs = pl->group_off[kMaxGroups];
     PCHK(hipMemcpyAsync(d_goff, pl->group_off, sizeof(long long) * (kMaxGroups + 1), hipMemcpyHostToDevice, st));
-    PCHK(hipMalloc(&pl->d_pairs, sizeof(PairRec) * (size_t)(pl->n_pairs > 0 ? pl->n_pairs : 1)));
-    pl->allocations.push_back(pl->d_pairs);
+    PCHK(own(&pl->d_pairs, sizeof(PairRec) * (size_t)(pl->n_pairs > 0 ? pl->n_pairs : 1)));
     if (pl->n_pairs > 0) {
         hipLaunchKernelGGL(k_pairs<true>, dim3(nblk(nn, 256)), dim3(256), 0, st, in.ps, in.pc,
                            (unsigned long long *)nullptr, (const long long *)d_goff, d_gcur, pl->d_pairs, d_err);
@@ -451,11 +488,11 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         unsigned *d_hist = nullptr, *d_keys = nullptr, *d_hcur = nullptr;
         long long *d_hoff = nullptr;
         PairRec *sorted = nullptr;
-        PCHK(hipMalloc(&d_hist, sizeof(unsigned) * (size_t)nkeys));
-        PCHK(hipMalloc(&d_hcur, sizeof(unsigned) * (size_t)nkeys));
-        PCHK(hipMalloc(&d_hoff, sizeof(long long) * (size_t)(nkeys + 1)));
-        PCHK(hipMalloc(&d_keys, sizeof(unsigned) * (size_t)pl->n_pairs));
-        PCHK(hipMalloc(&sorted, sizeof(PairRec) * (size_t)pl->n_pairs));
+        PCHK(tmp.alloc(&d_hist, sizeof(unsigned) * (size_t)nkeys));
+        PCHK(tmp.alloc(&d_hcur, sizeof(unsigned) * (size_t)nkeys));
+        PCHK(tmp.alloc(&d_hoff, sizeof(long long) * (size_t)(nkeys + 1)));
+        PCHK(tmp.alloc(&d_keys, sizeof(unsigned) * (size_t)pl->n_pairs));
+        PCHK(own(&sorted, sizeof(PairRec) * (size_t)pl->n_pairs));
         PCHK(hipMemsetAsync(d_hist, 0, sizeof(unsigned) * (size_t)nkeys, st));
         PCHK(hipMemsetAsync(d_hcur, 0, sizeof(unsigned) * (size_t)nkeys, st));
         hipLaunchKernelGGL(k_cell_count, dim3(nblk(pl->n_pairs, 256)), dim3(256), 0, st,
@@ -467,16 +504,17 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
                            (const long long *)d_hoff, d_hcur, (const unsigned *)d_hist, sorted, d_err);
         PCHK(hipGetLastError());
         PCHK(hipStreamSynchronize(st));
+        // the sorted copy replaces the unsorted records in the plan
+        for (auto &a : pl->allocations)
+            if (a == (void *)pl->d_pairs) a = nullptr;
         (void)hipFree(pl->d_pairs);
-        pl->allocations.back() = sorted;
         pl->d_pairs = sorted;
-        (void)hipFree(d_hist);
-        (void)hipFree(d_hcur);
-        (void)hipFree(d_hoff);
-        (void)hipFree(d_keys);
+        tmp.release(d_hist);
+        tmp.release(d_hcur);
+        tmp.release(d_hoff);
+        tmp.release(d_keys);
     }
-    PCHK(hipMalloc(&pl->d_rrec, sizeof(RhoRec) * (size_t)(pl->n_pairs > 0 ? pl->n_pairs : 1)));
-    pl->allocations.push_back(pl->d_rrec);
+    PCHK(own(&pl->d_rrec, sizeof(RhoRec) * (size_t)(pl->n_pairs > 0 ? pl->n_pairs : 1)));
     if (pl->n_pairs > 0) {
         hipLaunchKernelGGL(k_rho_records, dim3(nblk(pl->n_pairs, 256)), dim3(256), 0, st,
                            (const PairRec *)pl->d_pairs, pl->n_pairs, pl->d_rrec);
@@ -494,17 +532,16 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     long long *d_flag_off = nullptr;
     double *d_stats = nullptr;
     int *d_maxw = nullptr;
-    PCHK(hipMalloc(&d_maxw, 2 * sizeof(int)));
+    PCHK(tmp.alloc(&d_maxw, 2 * sizeof(int)));
     PCHK(hipMemsetAsync(d_maxw, 0, 2 * sizeof(int), st));
-    PCHK(hipMalloc(&d_cnt_base, sizeof(long long) * (kMaxGroups + 1)));
+    PCHK(tmp.alloc(&d_cnt_base, sizeof(long long) * (kMaxGroups + 1)));
     PCHK(hipMemcpyAsync(d_cnt_base, pl->cnt_base, sizeof(long long) * (kMaxGroups + 1), hipMemcpyHostToDevice, st));
-    PCHK(hipMalloc(&d_cnt, sizeof(unsigned) * (size_t)(ncnt + 1)));
-    PCHK(hipMalloc(&d_cur, sizeof(unsigned) * (size_t)(ncnt + 1)));
-    PCHK(hipMalloc(&d_flags, sizeof(unsigned) * (size_t)(ncnt + 1)));
-    PCHK(hipMalloc(&d_flag_off, sizeof(long long) * (size_t)(ncnt + 2)));
-    PCHK(hipMalloc(&d_stats, sizeof(double) * 2 * kMaxGroups));
-    PCHK(hipMalloc(&pl->d_inc_off, sizeof(long long) * (size_t)(ncnt + 2)));
-    pl->allocations.push_back(pl->d_inc_off);
+    PCHK(tmp.alloc(&d_cnt, sizeof(unsigned) * (size_t)(ncnt + 1)));
+    PCHK(tmp.alloc(&d_cur, sizeof(unsigned) * (size_t)(ncnt + 1)));
+    PCHK(tmp.alloc(&d_flags, sizeof(unsigned) * (size_t)(ncnt + 1)));
+    PCHK(tmp.alloc(&d_flag_off, sizeof(long long) * (size_t)(ncnt + 2)));
+    PCHK(tmp.alloc(&d_stats, sizeof(double) * 2 * kMaxGroups));
+    PCHK(own(&pl->d_inc_off, sizeof(long long) * (size_t)(ncnt + 2)));
     PCHK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned) * (size_t)(ncnt + 1), st));
     PCHK(hipMemsetAsync(d_cur, 0, sizeof(unsigned) * (size_t)(ncnt + 1), st));
     PCHK(hipMemsetAsync(d_stats, 0, sizeof(double) * 2 * kMaxGroups, st));
@@ -517,8 +554,7 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     PCHK(exclusive_scan<unsigned>(d_cnt, ncnt, pl->d_inc_off, st));
     PCHK(hipMemcpyAsync(&pl->n_inc, pl->d_inc_off + ncnt, sizeof(long long), hipMemcpyDeviceToHost, st));
     PCHK(hipStreamSynchronize(st));
-    PCHK(hipMalloc(&pl->d_inc, sizeof(int2) * (size_t)(pl->n_inc > 0 ? pl->n_inc : 1)));
-    pl->allocations.push_back(pl->d_inc);
+    PCHK(own(&pl->d_inc, sizeof(int2) * (size_t)(pl->n_inc > 0 ? pl->n_inc : 1)));
     if (pl->n_pairs > 0) {
         hipLaunchKernelGGL(k_incidences<true>, dim3(nblk(pl->n_pairs, 256)), dim3(256), 0, st,
                            (const PairRec *)pl->d_pairs, pl->n_pairs, in.pc, (const long long *)d_cnt_base,
@@ -535,8 +571,7 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     long long nblk_total = 0;
     PCHK(hipMemcpyAsync(&nblk_total, d_flag_off + ncnt, sizeof(long long), hipMemcpyDeviceToHost, st));
     PCHK(hipStreamSynchronize(st));
-    PCHK(hipMalloc(&pl->d_blk, sizeof(int) * (size_t)(nblk_total > 0 ? nblk_total : 1)));
-    pl->allocations.push_back(pl->d_blk);
+    PCHK(own(&pl->d_blk, sizeof(int) * (size_t)(nblk_total > 0 ? nblk_total : 1)));
     if (ncnt > 0) {
         hipLaunchKernelGGL(k_compact_blocks, dim3(nblk(ncnt, 256)), dim3(256), 0, st, (const unsigned *)d_cnt,
                            ncnt, (const long long *)d_flag_off, (const long long *)d_cnt_base, ngroups, pl->d_blk);
@@ -558,8 +593,16 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     pl->max_axis_blocks = maxwb[1];
     for (int g = 0; g <= kMaxGroups; ++g) pl->blk_off[g] = flag_at[g];
     if (errf & 1) { err = "partitioner count and fill passes disagree"; return hipErrorUnknown; }
-    if (errf & 2) { err = "a truncation sphere reaches beyond 127 cells (fold shift out of range)"; return hipErrorInvalidValue; }
-    if (maxw > kMaxBoxWidth) { err = "a truncation sphere is wider than the supported box (" + std::to_string(maxw) + " points)"; return hipErrorInvalidValue; }
+    if (errf & 2) {
+        err = "a truncation sphere reaches beyond 127 cells (fold shift out of range)";
+        unsupported = true;
+        return hipErrorInvalidValue;
+    }
+    if (maxw > kMaxBoxWidth) {
+        err = "a truncation sphere is wider than the supported box (" + std::to_string(maxw) + " points)";
+        unsupported = true;
+        return hipErrorInvalidValue;
+    }
 
     // work statistics and the flop model
     gpw_plan_info &I = pl->info;
@@ -600,17 +643,6 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         I.flops_mat_exec += (mat_tensor(la, lb) ? 2.0 * L + 3.0 : f1) * blkpts;
     }
 
-    (void)hipFree(d_gcnt);
-    (void)hipFree(d_gcur);
-    (void)hipFree(d_goff);
-    (void)hipFree(d_cnt_base);
-    (void)hipFree(d_cnt);
-    (void)hipFree(d_cur);
-    (void)hipFree(d_flags);
-    (void)hipFree(d_flag_off);
-    (void)hipFree(d_stats);
-    (void)hipFree(d_maxw);
-    (void)hipFree(d_err);
     return hipSuccess;
 #undef PCHK
 }

@@ -240,10 +240,16 @@ class GPUExecutor:
         self.sizes[key] = int(info["device_bytes"]) + poisson_bytes
         n2 = 8 * info["n_ao"] ** 2
         grids = 8 * ngrid
-        blocks = 8 * 64 * sum(int(np.prod([(m + 3) // 4 for m in mesh])) for mesh in info["mesh"])
-        packed = 8 * 100 * sum(info["n_pairs"])             # packed D sub-blocks, at most (d|d)
-        common = n2 + 2 * grids + 16 * fine * 3 + max(packed, blocks)
-        self.req_sizes[key] = {FOCK: common + n2, GRAD: common + n2 + 24 * info["natm"]}
+        # the library's own scratch of each operation (packed D of the collocation;
+        # block-ordered potentials, with their periodic column extension, of the
+        # integration and the gradient; the symmetrised D of the gradient)
+        scr_rho, scr_mat, scr_grad = (int(x) for x in info["scratch_bytes"])
+        # D, the level densities and then potentials, the Poisson step's FFT
+        # temporaries; the collocation's and the second stage's scratch never
+        # coexist within one request
+        common = n2 + 2 * grids + 16 * fine * 3
+        self.req_sizes[key] = {FOCK: common + n2 + max(scr_rho, scr_mat),
+                               GRAD: common + 24 * info["natm"] + max(scr_rho, scr_grad)}
         self.n_occ[key] = system.n_occ
         if resident:
             self.plans[key] = (g, p)
