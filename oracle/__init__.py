@@ -61,7 +61,9 @@ def _load():
     if _lib is None:
         _lib = C.CDLL(build())
         for name in ("oracle_rho", "oracle_rho_points", "oracle_mat", "oracle_mat_blocks",
-                     "oracle_grad", "oracle_count_pairs", "oracle_meshes", "oracle_num_threads"):
+                     "oracle_grad", "oracle_count_pairs", "oracle_meshes", "oracle_num_threads",
+                     "oracle_tau", "oracle_tau_points", "oracle_mat_tau", "oracle_mat_tau_blocks",
+                     "oracle_grad_tau"):
             getattr(_lib, name).restype = C.c_int
     return _lib
 
@@ -218,6 +220,76 @@ class Oracle:
             raise MemoryError("oracle_grad: allocation failed")
         self.counts = cnt
         return out
+
+    # -- meta-GGA: kinetic energy density terms -----------------------------
+    def tau_density(self, D):
+        """tau_l = 1/2 sum D grad(phi) . grad(phi) on every level."""
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        total = sum(m[0] * m[1] * m[2] for m in self.meshes)
+        out = np.zeros(total, dtype=np.float64)
+        cnt = np.zeros(16, dtype=np.int64)
+        if _load().oracle_tau(C.byref(self._st), _dp(D), _dp(out), _lp(cnt)) != 0:
+            raise MemoryError("oracle_tau: allocation failed")
+        self.counts = cnt
+        return self._split(out)
+
+    def tau_points(self, D, level, flat_idx):
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        idx = np.ascontiguousarray(flat_idx, dtype=np.int64)
+        out = np.zeros(len(idx), dtype=np.float64)
+        cnt = np.zeros(16, dtype=np.int64)
+        if _load().oracle_tau_points(C.byref(self._st), _dp(D), C.c_int(level), C.c_long(len(idx)),
+                                     _lp(idx), _dp(out), _lp(cnt)) != 0:
+            raise MemoryError("oracle_tau_points: allocation failed")
+        self.counts = cnt
+        return out
+
+    def mat_tau(self, V):
+        """The kinetic-energy-density term of the matrix for level potentials vtau."""
+        v = self._concat(V)
+        out = np.zeros((self.n_ao, self.n_ao), dtype=np.float64)
+        cnt = np.zeros(16, dtype=np.int64)
+        if _load().oracle_mat_tau(C.byref(self._st), _dp(v), _dp(out), _lp(cnt)) != 0:
+            raise MemoryError("oracle_mat_tau: allocation failed")
+        self.counts = cnt
+        return out
+
+    def mat_tau_blocks(self, V, shell_pairs):
+        v = self._concat(V)
+        ns = self.s.nshell
+        off = self.s.ao_offsets()
+        slot = -np.ones(ns * ns, dtype=np.int64)
+        pos = 0
+        sizes = []
+        for (a, b) in shell_pairs:
+            na = int(off[a + 1] - off[a])
+            nb = int(off[b + 1] - off[b])
+            slot[a * ns + b] = pos
+            sizes.append((pos, na, nb))
+            pos += na * nb
+        out = np.zeros(max(pos, 1), dtype=np.float64)
+        cnt = np.zeros(16, dtype=np.int64)
+        if _load().oracle_mat_tau_blocks(C.byref(self._st), _dp(v), _lp(slot), C.c_long(max(pos, 1)),
+                                         _dp(out), _lp(cnt)) != 0:
+            raise MemoryError("oracle_mat_tau_blocks: allocation failed")
+        self.counts = cnt
+        return [out[p:p + na * nb].reshape(na, nb) for (p, na, nb) in sizes]
+
+    def grad_tau(self, D, V):
+        """dE_tau/dR with E_tau = sum_l w_l <vtau_l, tau_l(D)> at fixed D and vtau."""
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        v = self._concat(V)
+        out = np.zeros((self.s.natm, 3), dtype=np.float64)
+        cnt = np.zeros(16, dtype=np.int64)
+        if _load().oracle_grad_tau(C.byref(self._st), _dp(D), _dp(v), _dp(out), _lp(cnt)) != 0:
+            raise MemoryError("oracle_grad_tau: allocation failed")
+        self.counts = cnt
+        return out
+
+    def energy_tau(self, D, V):
+        """E_tau = sum_l w_l <vtau_l, tau_l(D)>."""
+        t = self.tau_density(D)
+        return float(sum(w * float(np.vdot(v, r)) for w, v, r in zip(self.weights(), V, t)))
 
     def count_pairs(self):
         out = np.zeros(self.nlevels, dtype=np.int64)

@@ -29,6 +29,23 @@
  *   factors of every ordered pair are differentiated and credited to their
  *   atoms (Sec. III.B, Alg. 3).
  *
+ * Meta-GGA terms (Sec. II, the kinetic energy density and Eq. (J_metaGGA);
+ * Sec. III.B, the substitution of the pair function by grad g_a . grad g_b
+ * stated with Algs. 1-3):
+ *
+ *   tau_l[j mod N] = 1/2 sum over the same ordered pair images and points of
+ *                    sum_{mu nu} D_{mu nu} c_ak c_bl grad G_{ak,mu}(x_j) . grad G_{bl,nu}(x_j - T)
+ *   Mtau_{mu nu}   = sum_l w_l sum over the same terms with D replaced by
+ *                    vtau_l[j mod N]: the variational derivative of
+ *                    E_tau = sum_l w_l <vtau_l, tau_l(D)> with respect to D
+ *   gradtau_X      = d/dR_X of E_tau at fixed D and vtau (second derivatives of
+ *                    the primitives)
+ *
+ *   The factor 1/2 of the kinetic energy density is kept in all three (the
+ *   paper's integration note keeps it, Eq. (J_metaGGA) and its gradient note
+ *   drop it; only with it are the three mutually consistent derivatives of
+ *   E_tau).
+ *
  * Truncation (reading of Sec. III.A, Eq. (cut), applied to the pair product):
  *   K = c_ak c_bl exp(-a_k a_l / (a_k + a_l) |A - B - T|^2), alpha_p = a_k + a_l,
  *   P = (a_k A + a_l (B + T)) / alpha_p, L = l_a + l_b,
@@ -243,7 +260,47 @@ static void tab1d(double C, double a, double h, long lo, long n, int lmax, doubl
     }
 }
 
-enum { MODE_RHO = 0, MODE_MAT = 1, MODE_GRAD = 2 };
+enum { MODE_RHO = 0, MODE_MAT = 1, MODE_GRAD = 2, MODE_TAU = 3, MODE_MAT_TAU = 4, MODE_GRAD_TAU = 5 };
+
+/* First and second derivative along one axis of (x-C)^i exp(-a (x-C)^2) at
+ * point t, from the table g of (x-C)^k exp(-a (x-C)^2), k = 0..lmax:
+ *   d/dx   = i (x-C)^(i-1) e - 2a (x-C)^(i+1) e
+ *   d2/dx2 = i(i-1) (x-C)^(i-2) e - 2a(2i+1) (x-C)^i e + 4a^2 (x-C)^(i+2) e */
+static double tab_d1(const double *g, long n, long t, int i, double a)
+{
+    double v = -2.0 * a * g[(i + 1) * n + t];
+    if (i >= 1) v += i * g[(i - 1) * n + t];
+    return v;
+}
+
+static double tab_d2(const double *g, long n, long t, int i, double a)
+{
+    double v = -2.0 * a * (2 * i + 1) * g[i * n + t] + 4.0 * a * a * g[(i + 2) * n + t];
+    if (i >= 2) v += i * (i - 1) * g[(i - 2) * n + t];
+    return v;
+}
+
+/* grad G_mu(x) along axis d (the derivative with respect to r), a primitive
+ * with Cartesian exponents e[3] tabulated in g[3] at point tt[3]. */
+static double cart_d1(double *const *g, const long *n, const long *tt, const int *e, double a, int d)
+{
+    double v = 1.0;
+    for (int k = 0; k < 3; ++k)
+        v *= (k == d) ? tab_d1(g[k], n[k], tt[k], e[k], a) : g[k][e[k] * n[k] + tt[k]];
+    return v;
+}
+
+/* d2 G_mu / dr_d dr_f */
+static double cart_d2(double *const *g, const long *n, const long *tt, const int *e, double a, int d, int f)
+{
+    double v = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        if (d == f && k == d) v *= tab_d2(g[k], n[k], tt[k], e[k], a);
+        else if (k == d || k == f) v *= tab_d1(g[k], n[k], tt[k], e[k], a);
+        else v *= g[k][e[k] * n[k] + tt[k]];
+    }
+    return v;
+}
 
 typedef struct {
     int mode;
@@ -284,10 +341,15 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
     /* sampled outputs: a pair image that cannot contribute is skipped before
      * anything is tabulated */
     if (c->nsamp > 0 && lv != c->samp_level) return;
-    if (c->mode == MODE_MAT && c->sp_slot && c->sp_slot[(long)p->sa * s->nshell + p->sb] < 0) return;
+    if ((c->mode == MODE_MAT || c->mode == MODE_MAT_TAU) && c->sp_slot &&
+        c->sp_slot[(long)p->sa * s->nshell + p->sb] < 0)
+        return;
     const int la = p->la, lb = p->lb, na = ncart(la), nb = ncart(lb);
-    const int ea = (c->mode == MODE_GRAD) ? la + 1 : la;
-    const int eb = (c->mode == MODE_GRAD) ? lb + 1 : lb;
+    /* table depth: the powers the mode's derivatives reach */
+    const int extra = c->mode == MODE_GRAD ? 1 : c->mode == MODE_TAU || c->mode == MODE_MAT_TAU ? 1
+                      : c->mode == MODE_GRAD_TAU ? 2 : 0;
+    const int ea = la + extra;
+    const int eb = lb + extra;
     double *ga[3], *gb[3];
     for (int d = 0; d < 3; ++d) {
         ga[d] = (double *)malloc(sizeof(double) * (ea + 1) * n[d]);
@@ -343,6 +405,53 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
                     for (int m = 0; m < nb; ++m)
                         Gb[m] = gb[0][bx[m][0] * n[0] + tx] * gb[1][bx[m][1] * n[1] + ty] *
                                 gb[2][bx[m][2] * n[2] + tz];
+                    if (c->mode >= MODE_TAU) {
+                        long tt[3] = {tx, ty, tz};
+                        double Da[10][3], Db[10][3];   /* grad G along each axis */
+                        for (int m = 0; m < na; ++m)
+                            for (int d = 0; d < 3; ++d) Da[m][d] = cart_d1(ga, n, tt, ax[m], p->aa, d);
+                        for (int m = 0; m < nb; ++m)
+                            for (int d = 0; d < 3; ++d) Db[m][d] = cart_d1(gb, n, tt, bx[m], p->ab, d);
+                        if (c->mode == MODE_TAU) {
+                            double acc = 0.0;
+                            for (int i = 0; i < na; ++i)
+                                for (int j = 0; j < nb; ++j) {
+                                    double dot = Da[i][0] * Db[j][0] + Da[i][1] * Db[j][1] + Da[i][2] * Db[j][2];
+                                    acc += c->D[(long)(mu0 + i) * c->n_ao + nu0 + j] * dot;
+                                }
+                            if (c->nsamp > 0) out[sidx] += 0.5 * cc * acc;
+                            else out[c->lvl_off[lv] + wflat] += 0.5 * cc * acc;
+                        } else if (c->mode == MODE_MAT_TAU) {
+                            double f = 0.5 * w * c->V[c->lvl_off[lv] + wflat] * cc;
+                            for (int i = 0; i < na; ++i)
+                                for (int j = 0; j < nb; ++j) {
+                                    double dot = Da[i][0] * Db[j][0] + Da[i][1] * Db[j][1] + Da[i][2] * Db[j][2];
+                                    long o;
+                                    if (c->sp_slot) o = c->sp_slot[(long)p->sa * s->nshell + p->sb] + i * nb + j;
+                                    else o = (long)(mu0 + i) * c->n_ao + nu0 + j;
+                                    out[o] += f * dot;
+                                }
+                        } else {
+                            /* d/dA_e grad G_a = -d/dr_e grad G_a (G_a depends on r - A) */
+                            double f = 0.5 * w * c->V[c->lvl_off[lv] + wflat] * cc;
+                            double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+                            for (int i = 0; i < na; ++i)
+                                for (int j = 0; j < nb; ++j) {
+                                    double Dij = c->D[(long)(mu0 + i) * c->n_ao + nu0 + j];
+                                    if (Dij == 0.0) continue;
+                                    for (int e = 0; e < 3; ++e)
+                                        for (int d = 0; d < 3; ++d) {
+                                            gA[e] -= Dij * cart_d2(ga, n, tt, ax[i], p->aa, e, d) * Db[j][d];
+                                            gB[e] -= Dij * Da[i][d] * cart_d2(gb, n, tt, bx[j], p->ab, e, d);
+                                        }
+                                }
+                            for (int e = 0; e < 3; ++e) {
+                                out[3 * p->atom_a + e] += f * gA[e];
+                                out[3 * p->atom_b + e] += f * gB[e];
+                            }
+                        }
+                        continue;
+                    }
                     if (c->mode == MODE_RHO) {
                         double acc = 0.0;
                         for (int i = 0; i < na; ++i) {
@@ -536,6 +645,73 @@ int oracle_grad(const osys *s, const double *D, const double *V, double *grad, l
 {
     octx c;
     setup_ctx(s, &c, MODE_GRAD);
+    c.D = D;
+    c.V = V;
+    if (alloc_bufs(&c, 3L * s->natm)) { finish(&c, NULL, NULL); return -1; }
+    for_each_pair(s, eval_pair, &c);
+    finish(&c, grad, counts);
+    return 0;
+}
+
+/* Kinetic energy density tau on every level, concatenated in level order. */
+int oracle_tau(const osys *s, const double *D, double *tau, long *counts)
+{
+    octx c;
+    setup_ctx(s, &c, MODE_TAU);
+    c.D = D;
+    if (alloc_bufs(&c, c.lvl_off[s->nlevels])) { finish(&c, NULL, NULL); return -1; }
+    for_each_pair(s, eval_pair, &c);
+    finish(&c, tau, counts);
+    return 0;
+}
+
+/* tau at sampled wrapped points (flat C-order indices) of one level. */
+int oracle_tau_points(const osys *s, const double *D, int level, long npts,
+                      const long *idx, double *out, long *counts)
+{
+    octx c;
+    setup_ctx(s, &c, MODE_TAU);
+    c.D = D;
+    c.samp_level = level;
+    c.nsamp = npts;
+    c.samp_idx = idx;
+    if (alloc_bufs(&c, npts)) { finish(&c, NULL, NULL); return -1; }
+    if (npts > 0) for_each_pair(s, eval_pair, &c);
+    finish(&c, out, counts);
+    return 0;
+}
+
+/* The tau term of the matrix, from concatenated level potentials vtau. */
+int oracle_mat_tau(const osys *s, const double *V, double *M, long *counts)
+{
+    octx c;
+    setup_ctx(s, &c, MODE_MAT_TAU);
+    c.V = V;
+    if (alloc_bufs(&c, (long)c.n_ao * c.n_ao)) { finish(&c, NULL, NULL); return -1; }
+    for_each_pair(s, eval_pair, &c);
+    finish(&c, M, counts);
+    return 0;
+}
+
+/* Shell-pair blocks of the tau term of the matrix (as oracle_mat_blocks). */
+int oracle_mat_tau_blocks(const osys *s, const double *V, const long *sp_slot, long out_len,
+                          double *out, long *counts)
+{
+    octx c;
+    setup_ctx(s, &c, MODE_MAT_TAU);
+    c.V = V;
+    c.sp_slot = sp_slot;
+    if (alloc_bufs(&c, out_len)) { finish(&c, NULL, NULL); return -1; }
+    for_each_pair(s, eval_pair, &c);
+    finish(&c, out, counts);
+    return 0;
+}
+
+/* dE_tau/dR (natm x 3) of E_tau = sum_l w_l <vtau_l, tau_l(D)> at fixed D, vtau. */
+int oracle_grad_tau(const osys *s, const double *D, const double *V, double *grad, long *counts)
+{
+    octx c;
+    setup_ctx(s, &c, MODE_GRAD_TAU);
     c.D = D;
     c.V = V;
     if (alloc_bufs(&c, 3L * s->natm)) { finish(&c, NULL, NULL); return -1; }

@@ -203,3 +203,110 @@ def theta_mat_ones(sys, mesh, nimg=3):
                         K = wa * wb * math.exp(-ea * eb / p * float(np.sum((A - B) ** 2)))
                         M[a, b] += w * K * np.prod([theta_sum(p, h[d], P[d]) for d in range(3)])
     return M
+
+
+# ------------------------------------------------ kinetic energy density pins
+
+def brute_grad_chi(sys, mesh, nimg=2):
+    """grad chi[d, mu, point] on the C-ordered grid (no truncation): the
+    r-derivative of x^i y^j z^k exp(-a r^2) is (i x^(i-1) - 2 a x^(i+1)) y^j z^k
+    exp(-a r^2) along x, lattice-summed like ``brute_chi``."""
+    cell = np.asarray(sys.cell, dtype=np.float64)
+    n = np.asarray(mesh)
+    h = cell / n
+    ax = [np.arange(n[d]) * h[d] for d in range(3)]
+    X, Y, Z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    out = []
+    for s in range(sys.nshell):
+        l = int(sys.shell_l[s])
+        A = sys.coords[sys.shell_atom[s]]
+        p0, npr = int(sys.shell_prim0[s]), int(sys.shell_nprim[s])
+        comps = cart_list(l)
+        acc = np.zeros((3, len(comps), pts.shape[0]))
+        for T in _images(cell, nimg):
+            d = pts - (A + T)
+            r2 = np.einsum("ij,ij->i", d, d)
+            for k in range(npr):
+                a, c = sys.exps[p0 + k], sys.coefs[p0 + k]
+                e = c * np.exp(-a * r2)
+                for m, pw in enumerate(comps):
+                    for ax_ in range(3):
+                        term = np.ones(pts.shape[0])
+                        for q in range(3):
+                            if q == ax_:
+                                f = -2.0 * a * d[:, q] ** (pw[q] + 1)
+                                if pw[q] > 0:
+                                    f = f + pw[q] * d[:, q] ** (pw[q] - 1)
+                                term = term * f
+                            else:
+                                term = term * d[:, q] ** pw[q]
+                        acc[ax_, m] += term * e
+        out.append(acc)
+    return np.concatenate(out, axis=1)
+
+
+def brute_tau(gchi, D, mesh):
+    """tau = 1/2 sum_d sum_{mu nu} D_{mu nu} d_d chi_mu d_d chi_nu."""
+    return 0.5 * np.einsum("dmp,mn,dnp->p", gchi, D, gchi).reshape(tuple(mesh))
+
+
+def brute_mat_tau(gchi, v, w):
+    """M_tau = 1/2 w sum_d (d_d chi) diag(v) (d_d chi)^T."""
+    vv = v.ravel()[None, :]
+    return 0.5 * w * sum((gchi[d] * vv) @ gchi[d].T for d in range(3))
+
+
+def _dint1d(i, j, A, B, a, b):
+    """int d/dx[(x-A)^i e^(-a(x-A)^2)] d/dx[(x-B)^j e^(-b(x-B)^2)] dx, each
+    derivative being i (x-A)^(i-1) e - 2a (x-A)^(i+1) e."""
+    def terms(k, c):
+        t = [(k + 1, -2.0 * c)]
+        if k > 0:
+            t.append((k - 1, float(k)))
+        return t
+    return sum(ca * cb * _int1d(p, q, A, B, a, b) for (p, ca) in terms(i, a) for (q, cb) in terms(j, b))
+
+
+def kinetic(sys, nimg=3):
+    """Periodic kinetic matrix T_{mu nu} = 1/2 sum_T int grad phi_mu . grad phi_nu(. - T),
+    from closed-form 1-D Gaussian integrals."""
+    off = sys.ao_offsets()
+    prims = _prims(sys)
+    n = sys.n_ao
+    T_ = np.zeros((n, n))
+    cell = np.asarray(sys.cell, dtype=np.float64)
+    for a in range(sys.nshell):
+        A = sys.coords[sys.shell_atom[a]]
+        ca = cart_list(int(sys.shell_l[a]))
+        for b in range(sys.nshell):
+            B0 = sys.coords[sys.shell_atom[b]]
+            cb = cart_list(int(sys.shell_l[b]))
+            for Tv in _images(cell, nimg):
+                B = B0 + Tv
+                for (ea, wa) in prims[a]:
+                    for (eb, wb) in prims[b]:
+                        for i, pa in enumerate(ca):
+                            for j, pb in enumerate(cb):
+                                s1 = [_int1d(pa[d], pb[d], A[d], B[d], ea, eb) for d in range(3)]
+                                k1 = [_dint1d(pa[d], pb[d], A[d], B[d], ea, eb) for d in range(3)]
+                                T_[off[a] + i, off[b] + j] += 0.5 * wa * wb * (
+                                    k1[0] * s1[1] * s1[2] + s1[0] * k1[1] * s1[2] + s1[0] * s1[1] * k1[2])
+    return T_
+
+
+def kinetic_grad(sys, D, nimg=3, h=1e-4):
+    """sum_{mu nu} D_{mu nu} dT_{mu nu}/dR_X by central differences of the
+    closed-form T (natm x 3); the closed form is smooth, so h = 1e-4 gives ~1e-9."""
+    import copy
+    g = np.zeros((sys.natm, 3))
+    for X in range(sys.natm):
+        for d in range(3):
+            vals = []
+            for sgn in (1.0, -1.0):
+                s2 = copy.copy(sys)
+                s2.coords = sys.coords.copy()
+                s2.coords[X, d] += sgn * h
+                vals.append(float(np.sum(D * kinetic(s2, nimg))))
+            g[X, d] = (vals[0] - vals[1]) / (2 * h)
+    return g
