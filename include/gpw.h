@@ -205,6 +205,22 @@ typedef struct {
  * different tasks must not overlap.  Enqueued on stream. */
 gpw_status gpw_eval_batch(const gpw_task *tasks, int ntasks, void *stream);
 
+/* gpw_eval_mat without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result and kernels as gpw_eval_mat; the
+ * per-call scratch (the block-ordered copies of the level potentials) lives
+ * in a fixed array of GPW_NOALLOC_SCRATCH_BYTES (128 MiB) per device, which
+ * the library holds from the first plan built on that device until the
+ * process ends.  Calls make no hipMalloc, hipMallocAsync or hipFree.  A plan
+ * whose scratch (gpw_plan_info.scratch_bytes[GPW_OP_MAT]) exceeds that size
+ * is rejected with GPW_EBUDGET before anything is enqueued.  Every call on a
+ * device shares that device's array and overwrites it: calls that may
+ * overlap on one device (different streams without ordering between them)
+ * race and give undefined results; calls on one stream are ordered.  Nothing
+ * of a previous call's contents is read. */
+#define GPW_NOALLOC_SCRATCH_BYTES (128ull << 20)
+gpw_status gpw_eval_mat_noalloc(gpw_plan_t plan, const double *const *v, double *M, void *stream);
+
 /* Thread-local message describing the last failure in this thread. */
 const char *gpw_last_error(void);
 

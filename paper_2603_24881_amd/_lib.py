@@ -100,7 +100,8 @@ class gpw_task(C.Structure):
 
 
 EXPORTS = ("gpw_plan", "gpw_plan_destroy", "gpw_plan_query", "gpw_eval_rho", "gpw_eval_mat",
-           "gpw_eval_grad", "gpw_eval_batch", "gpw_last_error")
+           "gpw_eval_grad", "gpw_eval_batch", "gpw_eval_mat_noalloc", "gpw_last_error")
+GPW_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 _lib = None
 
@@ -121,6 +122,7 @@ def load(path: str = LIB_PATH):
     lib.gpw_eval_mat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_eval_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_eval_batch.argtypes = [C.POINTER(gpw_task), C.c_int, C.c_void_p]
+    lib.gpw_eval_mat_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_last_error.restype = C.c_char_p
     for name in EXPORTS:
         if name != "gpw_last_error":
@@ -292,6 +294,11 @@ def gpw_eval_rho(plan: PlanHandle, D, rho, stream=None):
 def gpw_eval_mat(plan: PlanHandle, v, M, stream=None):
     arr = _level_ptrs(plan, v, "v")
     _check(load().gpw_eval_mat(plan.handle, arr, _mat_ptr(plan, M, "M"), _stream_handle(stream)))
+
+
+def gpw_eval_mat_noalloc(plan: PlanHandle, v, M, stream=None):
+    arr = _level_ptrs(plan, v, "v")
+    _check(load().gpw_eval_mat_noalloc(plan.handle, arr, _mat_ptr(plan, M, "M"), _stream_handle(stream)))
 
 
 def gpw_eval_grad(plan: PlanHandle, D, v, grad, stream=None):

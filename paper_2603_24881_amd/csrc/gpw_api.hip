@@ -194,6 +194,13 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
         }
     }
+    {
+        // set-up of the allocation-free entry point on this device: look up the
+        // address of its fixed scratch array once, with the device current
+        unsigned char *scr = nullptr;
+        const hipError_t es = gpw::noalloc_scratch(pl->device, &scr);
+        if (es != hipSuccess) { free_plan(pl); return hip_fail(es, "gpw_plan: scratch symbol address"); }
+    }
     hipStream_t st = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e != hipSuccess) { free_plan(pl); return hip_fail(e, "gpw_plan: hipStreamCreate"); }
@@ -349,6 +356,23 @@ gpw_status gpw_eval_grad(gpw_plan_t plan, const double *D, const double *const *
 {
     gpw_task t{plan, GPW_OP_GRAD, D, v, nullptr, grad};
     return run_tasks(&t, 1, stream, "gpw_eval_grad");
+}
+
+gpw_status gpw_eval_mat_noalloc(gpw_plan_t plan, const double *const *v, double *M, void *stream)
+{
+    const gpw_task t{plan, GPW_OP_MAT, nullptr, v, nullptr, M};
+    TaskRef ref;
+    gpw_status s = check_task(t, ref, "gpw_eval_mat_noalloc");
+    if (s != GPW_OK) return s;
+    const size_t need = gpw::eval_scratch_bytes(plan, GPW_OP_MAT);
+    if (need > gpw::kNoAllocScratchBytes)
+        return fail(GPW_EBUDGET, "gpw_eval_mat_noalloc: the plan needs " + std::to_string(need) +
+                                     " bytes of scratch, above the fixed " +
+                                     std::to_string(gpw::kNoAllocScratchBytes) + " of this entry point");
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_eval_mat_noalloc");
+    const hipError_t e = gpw::eval_noalloc(ref, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_eval_mat_noalloc");
 }
 
 gpw_status gpw_eval_batch(const gpw_task *tasks, int ntasks, void *stream)

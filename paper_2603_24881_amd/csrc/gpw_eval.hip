@@ -32,6 +32,7 @@
 // same kernels in the same order.
 #include "gpw_internal.h"
 
+#include <mutex>
 #include <utility>
 
 namespace gpw {
@@ -1447,12 +1448,36 @@ static void dispatch_cls(int c, F &&f)
 
 static inline long long nb256(long long n) { return (n + 255) / 256; }
 
+// Growable array with room for N elements inline: the launch path of a
+// single evaluation stays inside the inline storage and so makes no host
+// allocation (the heap holds only what a large batch adds past N).
+template <typename T, int N>
+struct SmallVec {
+    T buf[N];
+    std::vector<T> more;
+    size_t n = 0;
+    size_t size() const { return n; }
+    T &operator[](size_t i) { return i < (size_t)N ? buf[i] : more[i - N]; }
+    const T &operator[](size_t i) const { return i < (size_t)N ? buf[i] : more[i - N]; }
+    void push_back(const T &x)
+    {
+        if (n < (size_t)N) buf[n] = x;
+        else more.push_back(x);
+        ++n;
+    }
+    void resize(size_t m)
+    {
+        if (m > (size_t)N) more.resize(m - N);
+        n = m;
+    }
+};
+
 // Segments of one (operation, class) and the launches that cover them, at
 // most kMaxSeg segments per launch.
 template <typename S>
 struct SegList {
-    std::vector<S> v;
-    std::vector<long long> items;
+    SmallVec<S, kMaxSeg> v;
+    SmallVec<long long, kMaxSeg> items;
     void add(const S &s, long long n)
     {
         if (n <= 0) return;
@@ -1535,19 +1560,29 @@ size_t eval_scratch_bytes(const gpw_plan_s *pl, int op)
     return pl->precision == GPW_FP32 ? task_scratch<float>(pl, op, 0, x) : task_scratch<double>(pl, op, 0, x);
 }
 
+// One batch of tasks of one precision.  Scratch: a stream-ordered allocation
+// of the batch's size, or, when ext is given, the caller's ext_cap bytes at
+// ext (then nothing is allocated or freed).
 template <typename T>
-static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
+static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned char *ext = nullptr,
+                          size_t ext_cap = 0)
 {
-    std::vector<TaskScratch> ts(n);
+    SmallVec<TaskScratch, 1> ts;
+    ts.resize((size_t)n);
     size_t bytes = 0;
     int emax_all = 1;
     for (int i = 0; i < n; ++i) {
         bytes += task_scratch<T>(tasks[i].pl, tasks[i].op, bytes, ts[i]);
         if (tasks[i].op != GPW_OP_RHO) emax_all = std::max(emax_all, tasks[i].pl->max_axis_blocks);
     }
-    unsigned char *scr = nullptr;
-    hipError_t e = hipMallocAsync((void **)&scr, bytes > 0 ? bytes : 256, st);
-    if (e != hipSuccess) return e;
+    unsigned char *scr = ext;
+    hipError_t e = hipSuccess;
+    if (ext) {
+        if (bytes > ext_cap) return hipErrorInvalidValue;
+    } else {
+        e = hipMallocAsync((void **)&scr, bytes > 0 ? bytes : 256, st);
+        if (e != hipSuccess) return e;
+    }
 
     // outputs to zero, symmetrised D of gradient tasks, block-ordered potentials
     SegList<FillSeg> fills;
@@ -1653,13 +1688,55 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st)
         });
     }
     e = hipGetLastError();
-    (void)hipFreeAsync(scr, st);
+    if (!ext) (void)hipFreeAsync(scr, st);
     return e;
 }
 
 size_t pair_kernel_lds_bytes(int emax, int precision)
 {
     return precision == GPW_FP32 ? PairSmem<float>::bytes(emax) : PairSmem<double>::bytes(emax);
+}
+
+// ------------------------------------------------- evaluation without allocation
+
+// Scratch of the allocation-free entry point: one copy per device, resident
+// from the library's first use of the device until the process ends.  Host
+// code never names it directly (on the host the name is only a stand-in for
+// the symbol): noalloc_scratch() looks up each device's address once, with
+// that device current, and every use goes through that address.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int dev, unsigned char **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev) return hipErrorInvalidDevice;   // the caller makes dev current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t eval_noalloc(const TaskRef &t, hipStream_t st)
+{
+    unsigned char *scr = nullptr;
+    hipError_t e = noalloc_scratch(t.pl->device, &scr);
+    if (e != hipSuccess) return e;
+    return t.pl->precision == GPW_FP32 ? batch_t<float>(&t, 1, st, scr, kNoAllocScratchBytes)
+                                       : batch_t<double>(&t, 1, st, scr, kNoAllocScratchBytes);
 }
 
 hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st)

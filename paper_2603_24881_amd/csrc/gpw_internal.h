@@ -304,6 +304,13 @@ struct TaskRef {
     double *out;
 };
 hipError_t eval_batch(const TaskRef *tasks, int n, hipStream_t st);
+// The allocation-free evaluation: scratch comes from a fixed per-device array
+// of kNoAllocScratchBytes (its size is checked by the caller beforehand).
+constexpr size_t kNoAllocScratchBytes = GPW_NOALLOC_SCRATCH_BYTES;
+hipError_t eval_noalloc(const TaskRef &t, hipStream_t st);
+// Address of that array on device dev, looked up on the first call for dev
+// (which must be the current device then) and cached.
+hipError_t noalloc_scratch(int dev, unsigned char **ptr);
 // Device scratch one evaluation of op (gpw_op) takes from the stream-ordered pool.
 size_t eval_scratch_bytes(const gpw_plan_s *pl, int op);
 // LDS bytes a workgroup of the pair-major kernels (mat, grad) needs for a plan

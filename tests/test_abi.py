@@ -78,6 +78,7 @@ def test_null_arguments():
     assert lib.gpw_eval_rho(None, None, None, None) == 1
     assert lib.gpw_eval_mat(None, None, None, None) == 1
     assert lib.gpw_eval_grad(None, None, None, None, None) == 1
+    assert lib.gpw_eval_mat_noalloc(None, None, None, None) == 1
     assert lib.gpw_eval_batch(None, -1, None) == 1
     assert lib.gpw_eval_batch(None, 0, None) == 0
     one = (_lib.gpw_task * 1)()
