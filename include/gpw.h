@@ -141,10 +141,17 @@ typedef struct {
     double flops_rho_exec, flops_mat_exec;
     long long device_bytes;                   /* device memory held by the plan */
     int max_box_width;                        /* widest bounding box (points per axis) */
-    long long scratch_bytes[3];               /* device scratch of one evaluation, indexed by the op
-                                                 value GPW_OP_RHO, _MAT, _GRAD; taken from the pool
-                                                 for the duration of the call (a batch takes the sum
-                                                 over its tasks) */
+    long long scratch_bytes[6];               /* device scratch of one evaluation, indexed by the op
+                                                 value GPW_OP_RHO .. GPW_OP_GRAD_TAU; taken from the
+                                                 pool for the duration of the call (a batch takes the
+                                                 sum over its tasks) */
+    /* the arithmetic of the other kernels, by the same rules as flops_rho_exec / _mat_exec:
+       grad accumulates moments of degree L + 1 (64 (2 (L+1) + 3) per incidence); the kinetic
+       energy density terms work two degrees higher: tau through its coefficient tensor of
+       degree L + 2 (the rho tensor count with L + 2), mat_tau and grad_tau through moments of
+       degree L + 2 and L + 3.  The per-pair-image formation of matrix elements and gradient
+       components from the moments is not counted. */
+    double flops_grad_exec, flops_tau_exec, flops_mat_tau_exec, flops_grad_tau_exec;
 } gpw_plan_info;
 
 /* Build a plan: screen primitive pair images, assign levels, compute their
@@ -186,16 +193,43 @@ gpw_status gpw_eval_mat(gpw_plan_t plan, const double *const *v, double *M, void
 gpw_status gpw_eval_grad(gpw_plan_t plan, const double *D, const double *const *v,
                          double *grad, void *stream);
 
+/* Kinetic energy density of meta-GGA functionals (Sec. II, the kinetic
+ * energy density and Eq. (J_metaGGA); Sec. III.B, the pair function of
+ * Algs. 1-3 replaced by the product of the two factors' gradients):
+ * tau_l(r) = 1/2 sum_{mu nu} D_{mu nu} grad phi_mu(r) . grad phi_nu(r) over the
+ * same pair images, levels and truncation spheres as gpw_eval_rho (the plan
+ * is shared).  D and tau as D and rho of gpw_eval_rho (tau[l] overwritten,
+ * unweighted).  Enqueued on stream. */
+gpw_status gpw_eval_tau(gpw_plan_t plan, const double *D, double *const *tau, void *stream);
+
+/* The kinetic-energy-density term of the matrix, the derivative of
+ * E_tau = sum_l w_l <vtau_l, tau_l(D)> with respect to D_{mu nu}:
+ * M_{mu nu} = 1/2 sum_l w_l sum_r vtau_l(r) grad phi_mu . grad phi_nu
+ * (Sec. II, Eq. (J_metaGGA); Sec. III.B with Alg. 2).  vtau, M as v, M of
+ * gpw_eval_mat (M overwritten, full symmetric).  Enqueued on stream. */
+gpw_status gpw_eval_mat_tau(gpw_plan_t plan, const double *const *vtau, double *M, void *stream);
+
+/* Nuclear gradient of E_tau at fixed D and vtau (Sec. III.B, the meta-GGA
+ * note with Alg. 3; second derivatives of the basis functions):
+ * grad[A][x] = d/dR_{A,x} sum_l w_l <vtau_l, tau_l(D; R)>.  Arguments as
+ * gpw_eval_grad (grad overwritten).  Enqueued on stream. */
+gpw_status gpw_eval_grad_tau(gpw_plan_t plan, const double *D, const double *const *vtau, double *grad,
+                             void *stream);
+
 /* One task of a batched launch. */
-typedef enum { GPW_OP_RHO = 0, GPW_OP_MAT = 1, GPW_OP_GRAD = 2 } gpw_op;
+typedef enum {
+    GPW_OP_RHO = 0, GPW_OP_MAT = 1, GPW_OP_GRAD = 2,
+    GPW_OP_TAU = 3, GPW_OP_MAT_TAU = 4, GPW_OP_GRAD_TAU = 5
+} gpw_op;
 
 typedef struct {
     gpw_plan_t plan;
     int op;                      /* gpw_op */
-    const double *D;             /* RHO, GRAD */
-    const double *const *v;      /* MAT, GRAD: host array of nlevels device pointers */
-    double *const *rho;          /* RHO: host array of nlevels device pointers */
-    double *out;                 /* MAT: M (n_ao x n_ao); GRAD: natm x 3 */
+    const double *D;             /* RHO, GRAD, TAU, GRAD_TAU */
+    const double *const *v;      /* MAT, GRAD, MAT_TAU, GRAD_TAU: host array of nlevels device pointers
+                                    (vtau for the _TAU operations) */
+    double *const *rho;          /* RHO, TAU: host array of nlevels device pointers (the output grids) */
+    double *out;                 /* MAT, MAT_TAU: M (n_ao x n_ao); GRAD, GRAD_TAU: natm x 3 */
 } gpw_task;
 
 /* Batched evaluation for serving: the tasks, possibly of different plans, run

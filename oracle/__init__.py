@@ -63,7 +63,7 @@ def _load():
         for name in ("oracle_rho", "oracle_rho_points", "oracle_mat", "oracle_mat_blocks",
                      "oracle_grad", "oracle_count_pairs", "oracle_meshes", "oracle_num_threads",
                      "oracle_tau", "oracle_tau_points", "oracle_mat_tau", "oracle_mat_tau_blocks",
-                     "oracle_grad_tau"):
+                     "oracle_grad_tau", "oracle_set_threads"):
             getattr(_lib, name).restype = C.c_int
     return _lib
 
@@ -82,6 +82,11 @@ def _lp(a):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """OpenMP threads of the following oracle calls; returns the count in effect."""
+    return int(_load().oracle_set_threads(C.c_int(int(n))))
 
 
 class Oracle:

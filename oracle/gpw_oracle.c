@@ -746,3 +746,14 @@ int oracle_count_pairs(const osys *s, long *per_level)
 }
 
 int oracle_num_threads(void) { return n_threads(); }
+
+/* Threads of the following calls (n >= 1); for timing runs at a set width. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return n_threads();
+}

@@ -19,7 +19,10 @@ LIB_PATH = os.path.join(HERE, "libgpw.so")
 GPW_MAX_LEVELS = 8
 GPW_NCLASS = 10
 GPW_FP64, GPW_FP32 = 0, 1
-GPW_OP_RHO, GPW_OP_MAT, GPW_OP_GRAD = 0, 1, 2
+GPW_OP_RHO, GPW_OP_MAT, GPW_OP_GRAD, GPW_OP_TAU, GPW_OP_MAT_TAU, GPW_OP_GRAD_TAU = 0, 1, 2, 3, 4, 5
+GRID_OPS = (GPW_OP_RHO, GPW_OP_TAU)
+MAT_OPS = (GPW_OP_MAT, GPW_OP_MAT_TAU)
+GRAD_OPS = (GPW_OP_GRAD, GPW_OP_GRAD_TAU)
 STATUS = {0: "GPW_OK", 1: "GPW_EINVAL", 2: "GPW_EUNSUPPORTED", 3: "GPW_ENOMEM",
           4: "GPW_EDEVICE", 5: "GPW_EBUDGET"}
 
@@ -84,7 +87,11 @@ class gpw_plan_info(C.Structure):
         ("flops_mat_exec", C.c_double),
         ("device_bytes", C.c_longlong),
         ("max_box_width", C.c_int),
-        ("scratch_bytes", C.c_longlong * 3),
+        ("scratch_bytes", C.c_longlong * 6),
+        ("flops_grad_exec", C.c_double),
+        ("flops_tau_exec", C.c_double),
+        ("flops_mat_tau_exec", C.c_double),
+        ("flops_grad_tau_exec", C.c_double),
     ]
 
 
@@ -100,7 +107,8 @@ class gpw_task(C.Structure):
 
 
 EXPORTS = ("gpw_plan", "gpw_plan_destroy", "gpw_plan_query", "gpw_eval_rho", "gpw_eval_mat",
-           "gpw_eval_grad", "gpw_eval_batch", "gpw_eval_mat_noalloc", "gpw_last_error")
+           "gpw_eval_grad", "gpw_eval_tau", "gpw_eval_mat_tau", "gpw_eval_grad_tau", "gpw_eval_batch",
+           "gpw_eval_mat_noalloc", "gpw_last_error")
 GPW_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 _lib = None
@@ -121,6 +129,9 @@ def load(path: str = LIB_PATH):
     lib.gpw_eval_rho.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_eval_mat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_eval_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_eval_tau.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_eval_mat_tau.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_eval_grad_tau.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_eval_batch.argtypes = [C.POINTER(gpw_task), C.c_int, C.c_void_p]
     lib.gpw_eval_mat_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_last_error.restype = C.c_char_p
@@ -260,6 +271,8 @@ class PlanHandle:
             "flops_rho_exec": info.flops_rho_exec, "flops_mat_exec": info.flops_mat_exec,
             "device_bytes": info.device_bytes, "max_box_width": info.max_box_width,
             "scratch_bytes": list(info.scratch_bytes),
+            "flops_grad_exec": info.flops_grad_exec, "flops_tau_exec": info.flops_tau_exec,
+            "flops_mat_tau_exec": info.flops_mat_tau_exec, "flops_grad_tau_exec": info.flops_grad_tau_exec,
         }
 
     def close(self):
@@ -296,6 +309,22 @@ def gpw_eval_mat(plan: PlanHandle, v, M, stream=None):
     _check(load().gpw_eval_mat(plan.handle, arr, _mat_ptr(plan, M, "M"), _stream_handle(stream)))
 
 
+def gpw_eval_tau(plan: PlanHandle, D, tau, stream=None):
+    arr = _level_ptrs(plan, tau, "tau")
+    _check(load().gpw_eval_tau(plan.handle, _mat_ptr(plan, D, "D"), arr, _stream_handle(stream)))
+
+
+def gpw_eval_mat_tau(plan: PlanHandle, vtau, M, stream=None):
+    arr = _level_ptrs(plan, vtau, "vtau")
+    _check(load().gpw_eval_mat_tau(plan.handle, arr, _mat_ptr(plan, M, "M"), _stream_handle(stream)))
+
+
+def gpw_eval_grad_tau(plan: PlanHandle, D, vtau, grad, stream=None):
+    arr = _level_ptrs(plan, vtau, "vtau")
+    _check(load().gpw_eval_grad_tau(plan.handle, _mat_ptr(plan, D, "D"), arr, _grad_ptr(plan, grad, "grad"),
+                                    _stream_handle(stream)))
+
+
 def gpw_eval_mat_noalloc(plan: PlanHandle, v, M, stream=None):
     arr = _level_ptrs(plan, v, "v")
     _check(load().gpw_eval_mat_noalloc(plan.handle, arr, _mat_ptr(plan, M, "M"), _stream_handle(stream)))
@@ -316,19 +345,19 @@ def gpw_eval_batch(tasks, stream=None):
         plan, op = t["plan"], int(t["op"])
         arr[i].plan = plan.handle
         arr[i].op = op
-        if op not in (GPW_OP_RHO, GPW_OP_MAT, GPW_OP_GRAD):
+        if op not in GRID_OPS + MAT_OPS + GRAD_OPS:
             raise ValueError(f"task {i}: unknown op {op}")
-        if op in (GPW_OP_RHO, GPW_OP_GRAD):
+        if op in GRID_OPS + GRAD_OPS:
             arr[i].D = _mat_ptr(plan, t.get("D"), f"task {i} D")
-        if op in (GPW_OP_MAT, GPW_OP_GRAD):
+        if op in MAT_OPS + GRAD_OPS:
             va = _level_ptrs(plan, t.get("v"), f"task {i} v")
             keep.append(va)
             arr[i].v = C.cast(va, C.c_void_p)
-        if op == GPW_OP_RHO:
+        if op in GRID_OPS:
             ra = _level_ptrs(plan, t.get("rho"), f"task {i} rho")
             keep.append(ra)
             arr[i].rho = C.cast(ra, C.c_void_p)
-        elif op == GPW_OP_MAT:
+        elif op in MAT_OPS:
             arr[i].out = _mat_ptr(plan, t.get("out"), f"task {i} M")
         else:
             arr[i].out = _grad_ptr(plan, t.get("out"), f"task {i} grad")

@@ -271,7 +271,8 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
                      (long long)sizeof(long long) * (pl->cnt_base[kMaxGroups] + 2) +
                      (long long)sizeof(int) * pl->blk_off[kMaxGroups] +
                      (long long)n_ps * (3 * sizeof(int) + 2 * sizeof(double)) + 24LL * pl->natm;
-    for (int op = GPW_OP_RHO; op <= GPW_OP_GRAD; ++op) I.scratch_bytes[op] = (long long)gpw::eval_scratch_bytes(pl, op);
+    for (int op = GPW_OP_RHO; op <= GPW_OP_GRAD_TAU; ++op)
+        I.scratch_bytes[op] = (long long)gpw::eval_scratch_bytes(pl, op);
     *out = pl;
     return GPW_OK;
 }
@@ -306,14 +307,17 @@ static gpw_status check_task(const gpw_task &t, TaskRef &out, const char *what)
     gpw_status s = GPW_OK;
     switch (t.op) {
     case GPW_OP_RHO:
+    case GPW_OP_TAU:
         if (!t.D) return fail(GPW_EINVAL, std::string(what) + ": NULL D");
         s = check_levels(t.plan, (const void *const *)t.rho, what);
         break;
     case GPW_OP_MAT:
+    case GPW_OP_MAT_TAU:
         if (!t.out) return fail(GPW_EINVAL, std::string(what) + ": NULL M");
         s = check_levels(t.plan, (const void *const *)t.v, what);
         break;
     case GPW_OP_GRAD:
+    case GPW_OP_GRAD_TAU:
         if (!t.D || !t.out) return fail(GPW_EINVAL, std::string(what) + ": NULL D or grad");
         s = check_levels(t.plan, (const void *const *)t.v, what);
         break;
@@ -356,6 +360,25 @@ gpw_status gpw_eval_grad(gpw_plan_t plan, const double *D, const double *const *
 {
     gpw_task t{plan, GPW_OP_GRAD, D, v, nullptr, grad};
     return run_tasks(&t, 1, stream, "gpw_eval_grad");
+}
+
+gpw_status gpw_eval_tau(gpw_plan_t plan, const double *D, double *const *tau, void *stream)
+{
+    gpw_task t{plan, GPW_OP_TAU, D, nullptr, tau, nullptr};
+    return run_tasks(&t, 1, stream, "gpw_eval_tau");
+}
+
+gpw_status gpw_eval_mat_tau(gpw_plan_t plan, const double *const *vtau, double *M, void *stream)
+{
+    gpw_task t{plan, GPW_OP_MAT_TAU, nullptr, vtau, nullptr, M};
+    return run_tasks(&t, 1, stream, "gpw_eval_mat_tau");
+}
+
+gpw_status gpw_eval_grad_tau(gpw_plan_t plan, const double *D, const double *const *vtau, double *grad,
+                             void *stream)
+{
+    gpw_task t{plan, GPW_OP_GRAD_TAU, D, vtau, nullptr, grad};
+    return run_tasks(&t, 1, stream, "gpw_eval_grad_tau");
 }
 
 gpw_status gpw_eval_mat_noalloc(gpw_plan_t plan, const double *const *v, double *M, void *stream)

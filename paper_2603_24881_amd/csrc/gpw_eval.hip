@@ -351,6 +351,97 @@ k_pack_density(SegTable<PackSeg> tab)
     for (int k = 0; k < K; ++k) out[k] = (T)C[k];
 }
 
+// ------------------------------------------------- kinetic energy density terms
+//
+// With a_i = (r-A)^a e^{-alpha |r-A|^2} and b_j likewise on B' = B + T, the
+// gradient of a factor along axis d is d_d a_i = a_d (r-A)^(a - e_d) e -
+// 2 alpha (r-A)^(a + e_d) e, so grad a_i . grad b_j is a polynomial of degree
+// l_a + l_b + 2 times the pair envelope: the same separable structure as the
+// density, two degrees higher (Sec. II, the meta-GGA terms; Sec. III.B).
+
+// Adds s (r-A)^(AX,AY,AZ) (r-B)^(BX,BY,BZ), with (x - B_x)^b expanded around A
+// (Eq. (binomial)), to the coefficient tensor C of degree LT; ab[d][p] =
+// (A_d - B_d)^p.
+template <int LT, int NP, int AX, int AY, int AZ, int BX, int BY, int BZ>
+__device__ __forceinline__ void add_product(double *C, double s, const double (*ab)[NP])
+{
+#pragma unroll
+    for (int kx = 0; kx <= BX; ++kx)
+#pragma unroll
+        for (int ky = 0; ky <= BY; ++ky)
+#pragma unroll
+            for (int kz = 0; kz <= BZ; ++kz)
+                C[tidx(LT, AX + kx, AY + ky, AZ + kz)] += s * (double)(binom(BX, kx) * binom(BY, ky) * binom(BZ, kz)) *
+                                                          ab[0][BX - kx] * ab[1][BY - ky] * ab[2][BZ - kz];
+}
+
+// d_D a_i d_D b_j of element (I, J) as four products of shifted monomials.
+template <int LA, int LB, int I, int J, int D>
+__device__ __forceinline__ void tau_dir(double *C, double dij, double two_a, double two_b, const double (*ab)[LB + 2])
+{
+    constexpr int LT = LA + LB + 2;
+    constexpr int ax = cart_lx(LA, I), ay = cart_ly(LA, I), az = LA - ax - ay;
+    constexpr int bx = cart_lx(LB, J), by = cart_ly(LB, J), bz = LB - bx - by;
+    constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
+    constexpr int ad = D == 0 ? ax : D == 1 ? ay : az;
+    constexpr int bd = D == 0 ? bx : D == 1 ? by : bz;
+    if constexpr (ad > 0 && bd > 0)
+        add_product<LT, LB + 2, ax - ex, ay - ey, az - ez, bx - ex, by - ey, bz - ez>(C, dij * (ad * bd), ab);
+    if constexpr (ad > 0)
+        add_product<LT, LB + 2, ax - ex, ay - ey, az - ez, bx + ex, by + ey, bz + ez>(C, -dij * ad * two_b, ab);
+    if constexpr (bd > 0)
+        add_product<LT, LB + 2, ax + ex, ay + ey, az + ez, bx - ex, by - ey, bz - ez>(C, -dij * bd * two_a, ab);
+    add_product<LT, LB + 2, ax + ex, ay + ey, az + ez, bx + ex, by + ey, bz + ez>(C, dij * two_a * two_b, ab);
+}
+template <int LA, int LB, int I, int J>
+__device__ __forceinline__ void tau_elem(double *C, double dij, double two_a, double two_b, const double (*ab)[LB + 2])
+{
+    tau_dir<LA, LB, I, J, 0>(C, dij, two_a, two_b, ab);
+    tau_dir<LA, LB, I, J, 1>(C, dij, two_a, two_b, ab);
+    tau_dir<LA, LB, I, J, 2>(C, dij, two_a, two_b, ab);
+}
+template <int LA, int LB, int... E>
+__device__ __forceinline__ void tau_terms(std::integer_sequence<int, E...>, double *C, const double *D, long long n,
+                                          long long a0, long long b0, double h, double two_a, double two_b,
+                                          const double (*ab)[LB + 2])
+{
+    constexpr int NB = ncart_c(LB);
+    ((tau_elem<LA, LB, E / NB, E % NB>(
+         C, h * (D[(a0 + E / NB) * n + b0 + E % NB] + D[(b0 + E % NB) * n + a0 + E / NB]), two_a, two_b, ab)),
+     ...);
+}
+
+// Kinetic-energy-density coefficient tensors of every pair image of one
+// (level, class) group, one thread per pair image: 1/2 Kw times the
+// symmetrised D sub-block contracted with grad a_i . grad b_j written as a
+// polynomial in r - A of degree l_a + l_b + 2 (FP64), packed per pair image.
+template <typename T, int LA, int LB>
+__global__ void __launch_bounds__(256)
+k_pack_tau(SegTable<PackSeg> tab)
+{
+    constexpr int NA = ncart_c(LA), NB = ncart_c(LB), LT = LA + LB + 2, K = ntab(LT);
+    const PackSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long lp = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
+    if (lp >= sg.count) return;
+    T *__restrict__ out = (T *)sg.out + lp * cstride<T>(K);
+    const PairRec &r = sg.pairs[lp];
+    double ab[3][LB + 2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ab[d][0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= LB + 1; ++k) ab[d][k] = ab[d][k - 1] * r.AB[d];
+    }
+    double C[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) C[k] = 0.0;
+    // 1/2 of tau times the 1/2 of the symmetrisation
+    tau_terms<LA, LB>(std::make_integer_sequence<int, NA * NB>{}, C, sg.D, sg.n, r.ao_a, r.ao_b, 0.25 * r.Kw,
+                      2.0 * r.aa, 2.0 * r.ab, ab);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = (T)C[k];
+}
+
 // Per-lane state of one pair image in the rho kernel.  The record and the D
 // sub-block of the next batch are copied from global memory straight into
 // LDS (16-byte direct-to-LDS loads, one instruction per 16-byte piece for
@@ -542,16 +633,24 @@ __device__ __forceinline__ void rho_points_direct(const T *Dk, double xa0, doubl
     }
 }
 
-// One lane's contributions, in the form the class uses.
-template <int LA, int LB, int NX, typename T>
+// One lane's contributions, in the form the class uses.  XL = 2: the
+// kinetic energy density, always through its coefficient tensor of degree
+// l_a + l_b + 2.
+template <int LA, int LB, int XL, int NX, typename T>
 __device__ __forceinline__ void rho_lane_points(const T *C, double xa0, double ya0, double za0, const double *AB,
                                                 const LevelGeom &G, const double *fx, const double *fy,
                                                 const double *fz, T ER, T on, int tx0, T *acc)
 {
-    if constexpr (rho_tensor(LA, LB))
-        rho_points<LA + LB, NX, T>(C, xa0, ya0, za0, G, fx, fy, fz, ER, on, tx0, acc);
+    if constexpr (XL > 0 || rho_tensor(LA, LB))
+        rho_points<LA + LB + XL, NX, T>(C, xa0, ya0, za0, G, fx, fy, fz, ER, on, tx0, acc);
     else
         rho_points_direct<LA, LB, NX, T>(C, xa0, ya0, za0, AB, G, fx, fy, fz, ER, on, tx0, acc);
+}
+
+// Coefficients per pair image in the packed rho / tau inputs.
+__host__ __device__ constexpr int grid_ncoef(int la, int lb, int xl)
+{
+    return xl > 0 ? ntab(la + lb + xl) : rho_ncoef(la, lb);
 }
 
 // Density of one (level, class) group on its nonempty 4x4x4 blocks.  One wave
@@ -563,13 +662,13 @@ __device__ __forceinline__ void rho_lane_points(const T *C, double xa0, double y
 // batches ahead; geometry and D one batch ahead, straight into LDS) are issued
 // before the current batch is computed, so their latency hides behind the
 // arithmetic.  NPASS splits the 64 points to bound the accumulator registers.
-template <int LA, int LB, int NPASS, int WPE, bool STG, bool PREF, typename T>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-k_rho(SegTable<RhoSeg> tab)
+// XL = 0: density; XL = 2: kinetic energy density (its coefficient tensor).
+template <int LA, int LB, int XL, int NPASS, bool STG, bool PREF, typename T>
+__device__ __forceinline__ void rho_blocks(const SegTable<RhoSeg> &tab)
 {
     constexpr int NX = 4 / NPASS;
     constexpr int NP = 16 * NX;
-    using Lane = RhoLane<T, rho_ncoef(LA, LB)>;
+    using Lane = RhoLane<T, grid_ncoef(LA, LB, XL)>;
     constexpr int LDSB = STG && Lane::STAGE > 32 * 65 * 8 ? Lane::STAGE : 32 * 65 * 8;
     // the batch staging area, and after the last batch the reduction buffer
     __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
@@ -643,7 +742,8 @@ k_rho(SegTable<RhoSeg> tab)
                 for (int q = 1; q < NPASS; ++q)
                     if (pass == q) fxp[ix] = fx[q * NX + ix];
             }
-            rho_lane_points<LA, LB, NX, T>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on, pass * NX, acc);
+            rho_lane_points<LA, LB, XL, NX, T>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on, pass * NX,
+                                               acc);
         }
         reduce_points<NP, T>(acc, red, pass * NP, mine);
     }
@@ -655,6 +755,24 @@ k_rho(SegTable<RhoSeg> tab)
     }
 }
 
+template <int LA, int LB, int NPASS, int WPE, bool STG, bool PREF, typename T>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_rho(SegTable<RhoSeg> tab)
+{
+    rho_blocks<LA, LB, 0, NPASS, STG, PREF, T>(tab);
+}
+
+// Kinetic energy density tau(r) = 1/2 sum D grad a . grad b (Sec. II, the
+// meta-GGA term; Sec. III.B, Alg. 1 with the pair function replaced by the
+// product of gradients): the density kernel with each pair image's
+// coefficient tensor of degree l_a + l_b + 2 (k_pack_tau), loaded per batch.
+template <int LA, int LB, int NPASS, int WPE, typename T>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_tau(SegTable<RhoSeg> tab)
+{
+    rho_blocks<LA, LB, 2, NPASS, false, false, T>(tab);
+}
+
 // The same density for the heavy classes with two waves per block: both
 // waves walk the block's list with the same lane = pair image mapping and
 // share one copy of every batch in LDS (double-buffered, each wave copying
@@ -664,7 +782,7 @@ template <int LA, int LB, int WPE, typename T>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_rho2(SegTable<RhoSeg> tab)
 {
-    using Lane = RhoLane<T, rho_ncoef(LA, LB)>;
+    using Lane = RhoLane<T, grid_ncoef(LA, LB, 0)>;
     constexpr int SB = Lane::STAGE;
     constexpr int REDB = 2 * 32 * 65 * 8;
     constexpr int LDSB = 2 * SB > REDB ? 2 * SB : REDB;
@@ -719,7 +837,7 @@ k_rho2(SegTable<RhoSeg> tab)
         const T on = act ? T(1) : T(0);
         const double xa0 = x0 - cur.A[0], ya0 = y0 - cur.A[1], za0 = z0 - cur.A[2];
         const double fxp[2] = {w ? fx[2] : fx[0], w ? fx[3] : fx[1]};
-        rho_lane_points<LA, LB, 2, T>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on, 2 * w, acc);
+        rho_lane_points<LA, LB, 0, 2, T>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on, 2 * w, acc);
     }
     __syncthreads();   // every read of the staging buffers is done
     double mine = 0.0;
@@ -774,6 +892,14 @@ template <> struct RhoSplit<3, 2> {
 template <> struct RhoSplit<3, 3> {
     static constexpr int npass = 4, wpe = 1, wpe2 = 1;
     static constexpr bool stage = false, two = false, pref = false;
+};
+
+// Kinetic energy density: points per pass and waves per SIMD by the degree
+// LT of the coefficient tensor (its ntab(LT) values and the accumulators
+// share the lane's registers).
+template <int LT> struct TauSplit {
+    static constexpr int npass = LT <= 4 ? 1 : LT == 5 ? 2 : 4;
+    static constexpr int wpe = LT <= 3 ? 2 : 1;
 };
 
 // ----------------------------------------------- pair-major traversal (mat, grad)
@@ -1147,7 +1273,7 @@ struct TensorVisit {
 // finish the sum, and lane 8q applies emit(k, sum) for k = chunk + q.  The
 // eight results of a chunk leave in parallel instead of one lane issuing
 // every atomic.
-constexpr size_t kRedBytes = (8 * 65 + 120) * sizeof(double);   // red[8][65] and up to ntab(7) moments
+constexpr size_t kRedBytes = (8 * 65 + 220) * sizeof(double);   // red[8][65] and up to ntab(9) moments
 template <int K, typename T, typename Emit>
 __device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit &&emit)
 {
@@ -1427,6 +1553,247 @@ k_grad(SegTable<PairSeg> tab)
     });
 }
 
+// ---------------------------------- kinetic-energy-density integration and gradient
+//
+// Matrix elements and gradients of the meta-GGA term from potential moments of
+// degree l_a + l_b + 2 (integration) and l_a + l_b + 3 (gradient).  One lane
+// per element (i, j): the element's Cartesian exponents are runtime values, so
+// every lane runs the same instructions and the elements of a pair image are
+// formed in parallel.  Each term is a product of one-axis factors, polynomials
+// in u = x - A_x, contracted with the moments.
+
+// (d/du)^N (u^p e^{-a u^2}) / e^{-a u^2}, coefficients of u^k for k = 0..W-1
+// (two_a = 2a): u^p; p u^(p-1) - 2a u^(p+1); p(p-1) u^(p-2) - 2a(2p+1) u^p +
+// 4a^2 u^(p+2).
+template <int W, int N>
+__device__ __forceinline__ void deriv_poly(int p, double two_a, double *g)
+{
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        double v;
+        if constexpr (N == 0)
+            v = k == p ? 1.0 : 0.0;
+        else if constexpr (N == 1)
+            v = (k == p - 1 ? (double)p : 0.0) + (k == p + 1 ? -two_a : 0.0);
+        else
+            v = (k == p - 2 ? (double)(p * (p - 1)) : 0.0) + (k == p ? -two_a * (2 * p + 1) : 0.0) +
+                (k == p + 2 ? two_a * two_a : 0.0);
+        g[k] = v;
+    }
+}
+
+// One-axis factor of a term: [(d/du)^NA (u^p e^{-a u^2})] [(d/dv)^NB
+// (v^q e^{-b v^2})] divided by both exponentials, with v = u + c (c = A - B),
+// as a polynomial in u: f[k], k = 0..W-1 (W at least p + q + NA + NB + 1 for
+// the lane's p <= PM, q <= QM; higher entries are zero).
+template <int W, int PM, int QM, int NA, int NB>
+__device__ __forceinline__ void axis_factor(int p, int q, double two_a, double two_b, double c, double *f)
+{
+    constexpr int GW = PM + NA + 1, HW = QM + NB + 1;
+    static_assert(GW + HW - 1 <= W, "factor width");
+    double g[GW], h[HW], hu[HW];
+    deriv_poly<GW, NA>(p, two_a, g);
+    deriv_poly<HW, NB>(q, two_b, h);
+    // h(u + c) by Horner's rule in (u + c)
+#pragma unroll
+    for (int k = 0; k < HW; ++k) hu[k] = 0.0;
+    hu[0] = h[HW - 1];
+#pragma unroll
+    for (int m = HW - 2; m >= 0; --m) {
+#pragma unroll
+        for (int k = HW - 1 - m; k >= 1; --k) hu[k] = hu[k - 1] + c * hu[k];
+        hu[0] = c * hu[0] + h[m];
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) f[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < GW; ++i)
+#pragma unroll
+        for (int j = 0; j < HW; ++j) f[i + j] += g[i] * hu[j];
+}
+
+// sum over kx + ky + kz <= LT of fx[kx] fy[ky] fz[kz] mom[tidx(LT, kx, ky, kz)]
+template <int LT, int W>
+__device__ __forceinline__ double contract3(const double *fx, const double *fy, const double *fz, const double *mom)
+{
+    double sx = 0.0;
+#pragma unroll
+    for (int kx = 0; kx < W && kx <= LT; ++kx) {
+        double sy = 0.0;
+#pragma unroll
+        for (int ky = 0; ky < W && kx + ky <= LT; ++ky) {
+            double sz = 0.0;
+#pragma unroll
+            for (int kz = 0; kz < W && kx + ky + kz <= LT; ++kz) sz += fz[kz] * mom[tidx(LT, kx, ky, kz)];
+            sy += fy[ky] * sz;
+        }
+        sx += fx[kx] * sy;
+    }
+    return sx;
+}
+
+__device__ __forceinline__ void cart_exps(int l, int n, int *e)
+{
+    e[0] = cart_lx(l, n);
+    e[1] = cart_ly(l, n);
+    e[2] = l - e[0] - e[1];
+}
+
+// sum_d of the d_d a_i d_d b_j moments (moments of degree l_a + l_b + 2).
+template <int LA, int LB>
+__device__ __forceinline__ double mat_tau_element(int i, int j, double two_a, double two_b, const double *AB,
+                                                  const double *mom)
+{
+    constexpr int LT = LA + LB + 2, W = LT + 1;
+    int a[3], b[3];
+    cart_exps(LA, i, a);
+    cart_exps(LB, j, b);
+    double f0[3][W], f1[3][W];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        axis_factor<W, LA, LB, 0, 0>(a[e], b[e], two_a, two_b, AB[e], f0[e]);
+        axis_factor<W, LA, LB, 1, 1>(a[e], b[e], two_a, two_b, AB[e], f1[e]);
+    }
+    return contract3<LT, W>(f1[0], f0[1], f0[2], mom) + contract3<LT, W>(f0[0], f1[1], f0[2], mom) +
+           contract3<LT, W>(f0[0], f0[1], f1[2], mom);
+}
+
+// d/dA_f and d/dB_f of sum_d d_d a_i d_d b_j (moments of degree
+// l_a + l_b + 3): with a_i depending on r - A, d/dA_f d_d a_i = -d_f d_d a_i,
+// and likewise for b_j; the results go to g6[f] (A) and g6[3 + f] (B).
+template <int LA, int LB>
+__device__ __forceinline__ void grad_tau_element(int i, int j, double two_a, double two_b, const double *AB,
+                                                 const double *mom, double *g6)
+{
+    constexpr int LT = LA + LB + 3, W = LT + 1;
+    int a[3], b[3];
+    cart_exps(LA, i, a);
+    cart_exps(LB, j, b);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g6[k] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // per axis: the factors of this direction d (on d: both differentiated
+        // once more or not; elsewhere: plain or one side differentiated)
+        double fp[3][W], fA[3][W], fB[3][W];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) {
+                axis_factor<W, LA, LB, 1, 1>(a[e], b[e], two_a, two_b, AB[e], fp[e]);
+                axis_factor<W, LA, LB, 2, 1>(a[e], b[e], two_a, two_b, AB[e], fA[e]);
+                axis_factor<W, LA, LB, 1, 2>(a[e], b[e], two_a, two_b, AB[e], fB[e]);
+            } else {
+                axis_factor<W, LA, LB, 0, 0>(a[e], b[e], two_a, two_b, AB[e], fp[e]);
+                axis_factor<W, LA, LB, 1, 0>(a[e], b[e], two_a, two_b, AB[e], fA[e]);
+                axis_factor<W, LA, LB, 0, 1>(a[e], b[e], two_a, two_b, AB[e], fB[e]);
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            g6[f] -= contract3<LT, W>(f == 0 ? fA[0] : fp[0], f == 1 ? fA[1] : fp[1], f == 2 ? fA[2] : fp[2], mom);
+            g6[3 + f] -= contract3<LT, W>(f == 0 ? fB[0] : fp[0], f == 1 ? fB[1] : fp[1], f == 2 ? fB[2] : fp[2],
+                                          mom);
+        }
+    }
+}
+
+// Moments of degree LT of one pair image (pair-major traversal), wave-summed
+// into LDS past the reduction area; returns their address.
+template <int LT, typename T>
+__device__ __forceinline__ const double *pair_moments(const PairSeg &sg, const PairRec &r, unsigned char *smem_raw)
+{
+    PtXY<T> *txy;
+    PtZ<T> *tz;
+    AxisBlock *bl;
+    int *cnt;
+    BlockRow *rows;
+    const LevelGeom &G = sg.G;
+    const int emax = sg.emax;
+    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
+    pair_setup<true, T>(r, G, txy, tz, bl, emax, cnt);
+    __syncthreads();
+    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
+    __syncthreads();
+    TensorVisit<LT, T> vis(r);
+    for_each_point<T>(txy, tz, emax, rows, nrows, sg.Vb, vis);
+    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+    double *red = reinterpret_cast<double *>(smem_raw);
+    double *mom = red + 8 * 65;
+    wave_reduce_emit<ntab(LT), T>(vis.Vm, red, [&](int k, double v) { mom[k] = v; });
+    __syncthreads();
+    return mom;
+}
+
+// Kinetic-energy-density term of the matrix (the variational derivative of
+// E_tau = sum_l w_l <vtau_l, tau_l(D)>): M_ij += 1/2 w sum_r vtau grad a_i .
+// grad b_j (Sec. II, Eq. (J_metaGGA); Sec. III.B with Alg. 2), one wave per
+// pair image, both triangles.
+template <int LA, int LB, typename T>
+__global__ void __launch_bounds__(64)
+k_mat_tau(SegTable<PairSeg> tab)
+{
+    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
+    extern __shared__ unsigned char smem_raw[];
+    const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
+    if (item >= sg.count) return;
+    const PairRec &r = sg.pairs[item];
+    const double *mom = pair_moments<LA + LB + 2, T>(sg, r, smem_raw);
+    const double AB[3] = {r.AB[0], r.AB[1], r.AB[2]};
+    // 1/2 of the meta-GGA term times the 1/2 that splits Kw over both triangles
+    const double scale = 0.25 * sg.G.w * r.Kw;
+    const int n_ao = sg.n_ao;
+#pragma unroll 1
+    for (int e0 = 0; e0 < NA * NB; e0 += 64) {
+        const int e = e0 + (int)threadIdx.x;
+        if (e < NA * NB) {
+            const int i = e / NB, j = e - (e / NB) * NB;
+            const double m = scale * mat_tau_element<LA, LB>(i, j, 2.0 * r.aa, 2.0 * r.ab, AB, mom);
+            atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], m);
+            atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], m);
+        }
+    }
+}
+
+// Nuclear gradient of E_tau at fixed D and vtau (Sec. III.B, the meta-GGA
+// note with Alg. 3): second derivatives of the first factor and first
+// derivatives of the second, one lane per element weighted by the symmetrised
+// D_ij, a wave sum of the six components, atomics into the two atoms.
+template <int LA, int LB, typename T>
+__global__ void __launch_bounds__(64)
+k_grad_tau(SegTable<PairSeg> tab)
+{
+    constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
+    extern __shared__ unsigned char smem_raw[];
+    const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
+    if (item >= sg.count) return;
+    const PairRec &r = sg.pairs[item];
+    const double *mom = pair_moments<LA + LB + 3, T>(sg, r, smem_raw);
+    const double AB[3] = {r.AB[0], r.AB[1], r.AB[2]};
+    const int n_ao = sg.n_ao;
+    const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
+    double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int e0 = 0; e0 < NA * NB; e0 += 64) {
+        const int e = e0 + (int)threadIdx.x;
+        if (e < NA * NB) {
+            const int i = e / NB, j = e - (e / NB) * NB;
+            double t6[6];
+            grad_tau_element<LA, LB>(i, j, 2.0 * r.aa, 2.0 * r.ab, AB, mom, t6);
+            const double dij = (double)Dp[(long long)i * n_ao + j];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) g6[k] += dij * t6[k];
+        }
+    }
+    // 1/2 of the meta-GGA term; Kw carries the weight of the canonical pair
+    const double scale = 0.5 * sg.G.w * r.Kw;
+    __syncthreads();   // every read of the moments is done
+    wave_reduce_emit<6, double>(g6, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
+        atomicAdd(&sg.out[3 * (k < 3 ? r.atom_a : r.atom_b) + (k < 3 ? k : k - 3)], scale * v);
+    });
+}
+
 // ------------------------------------------------------------ launchers
 
 template <typename F>
@@ -1524,17 +1891,23 @@ struct TaskScratch {
     long long voff[kMaxLevels];          // block-grid offsets of the levels (doubles)
 };
 
+// Operations that collocate onto the level grids (packed coefficients per
+// pair image), and those that read level potentials (block-ordered copies).
+static bool grid_op(int op) { return op == GPW_OP_RHO || op == GPW_OP_TAU; }
+static bool sym_op(int op) { return op == GPW_OP_GRAD || op == GPW_OP_GRAD_TAU; }
+static int extra_degree(int op) { return op == GPW_OP_TAU ? 2 : 0; }
+
 // Layout of one task's scratch (byte offsets from base) and its size.
 template <typename T>
 static size_t task_scratch(const gpw_plan_s *pl, int op, size_t base, TaskScratch &x)
 {
     size_t bytes = base;
-    if (op == GPW_OP_RHO) {
+    if (grid_op(op)) {
         x.dbase[0] = 0;
         for (int g = 0; g < kMaxGroups; ++g) {
             const int c = g % kNCls;
             x.dbase[g + 1] = x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) *
-                                              cstride<T>(rho_ncoef(cls_la(c), cls_lb(c)));
+                                              cstride<T>(grid_ncoef(cls_la(c), cls_lb(c), extra_degree(op)));
         }
         x.dpk = bytes;
         bytes += align256(sizeof(T) * (size_t)x.dbase[kMaxGroups]);
@@ -1546,7 +1919,7 @@ static size_t task_scratch(const gpw_plan_s *pl, int op, size_t base, TaskScratc
         }
         x.vb = bytes;
         bytes += align256(sizeof(double) * (size_t)(tot + 64 * kBlockCopyTail));
-        if (op == GPW_OP_GRAD) {
+        if (sym_op(op)) {
             x.ds = bytes;
             bytes += align256(sizeof(T) * (size_t)pl->n_ao * pl->n_ao);
         }
@@ -1573,7 +1946,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
     int emax_all = 1;
     for (int i = 0; i < n; ++i) {
         bytes += task_scratch<T>(tasks[i].pl, tasks[i].op, bytes, ts[i]);
-        if (tasks[i].op != GPW_OP_RHO) emax_all = std::max(emax_all, tasks[i].pl->max_axis_blocks);
+        if (!grid_op(tasks[i].op)) emax_all = std::max(emax_all, tasks[i].pl->max_axis_blocks);
     }
     unsigned char *scr = ext;
     hipError_t e = hipSuccess;
@@ -1591,18 +1964,19 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
     for (int i = 0; i < n; ++i) {
         const TaskRef &t = tasks[i];
         const gpw_plan_s *pl = t.pl;
-        if (t.op == GPW_OP_RHO) {
+        if (grid_op(t.op)) {
             for (int l = 0; l < pl->nlevels; ++l) fills.add({0, t.rho[l], pl->ngrid[l]}, nb256(pl->ngrid[l]));
             continue;
         }
-        const long long cnt = t.op == GPW_OP_MAT ? (long long)pl->n_ao * pl->n_ao : 3LL * pl->natm;
+        const long long cnt =
+            (t.op == GPW_OP_MAT || t.op == GPW_OP_MAT_TAU) ? (long long)pl->n_ao * pl->n_ao : 3LL * pl->natm;
         fills.add({0, t.out, cnt}, nb256(cnt));
         for (int l = 0; l < pl->nlevels; ++l) {
             const long long m = block_copy_blocks(pl, l) * 64;
             grids.add({0, t.v[l], (double *)(scr + ts[i].vb) + ts[i].voff[l], m, block_column(pl, l), pl->geom[l]},
                       nb256(m));
         }
-        if (t.op == GPW_OP_GRAD && pl->n_ao > 0) {
+        if (sym_op(t.op) && pl->n_ao > 0) {
             const int nt = (pl->n_ao + 31) / 32;
             syms.add({0, t.D, scr + ts[i].ds, pl->n_ao, nt}, (long long)nt * nt);
         }
@@ -1618,9 +1992,9 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
     }, false);
 
     for (int c = 0; c < kNCls; ++c) {
-        SegList<PackSeg> packs;
-        SegList<RhoSeg> rhos;
-        SegList<PairSeg> mats, grads;
+        SegList<PackSeg> packs, tpacks;
+        SegList<RhoSeg> rhos, taus;
+        SegList<PairSeg> mats, grads, mtaus, gtaus;
         for (int i = 0; i < n; ++i) {
             const TaskRef &t = tasks[i];
             const gpw_plan_s *pl = t.pl;
@@ -1629,10 +2003,13 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                 const int g = l * kNCls + c;
                 const long long np = pl->group_off[g + 1] - pl->group_off[g];
                 const PairRec *pairs = (const PairRec *)pl->d_pairs + pl->group_off[g];
-                if (t.op == GPW_OP_RHO) {
+                if (grid_op(t.op)) {
+                    const bool tau = t.op == GPW_OP_TAU;
                     T *Dpk = (T *)(scr + ts[i].dpk) + ts[i].dbase[g];
-                    const long long ne = rho_tensor(cls_la(c), cls_lb(c)) ? np : np * ncart(cls_la(c)) * ncart(cls_lb(c));
-                    packs.add({0, pairs, t.D, Dpk, ne, pl->n_ao}, nb256(ne));
+                    const long long ne = (tau || rho_tensor(cls_la(c), cls_lb(c)))
+                                             ? np
+                                             : np * ncart(cls_la(c)) * ncart(cls_lb(c));
+                    (tau ? tpacks : packs).add({0, pairs, t.D, Dpk, ne, pl->n_ao}, nb256(ne));
                     RhoSeg r;
                     r.item0 = 0;
                     r.count = pl->blk_off[g + 1] - pl->blk_off[g];
@@ -1644,20 +2021,24 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                     r.rho = t.rho[l];
                     r.p0 = (int)pl->group_off[g];
                     r.G = pl->geom[l];
-                    rhos.add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
+                    (tau ? taus : rhos).add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
                 } else {
                     PairSeg q;
                     q.item0 = 0;
                     q.count = np;
                     q.pairs = pairs;
-                    q.Dm = t.op == GPW_OP_GRAD ? (const void *)(scr + ts[i].ds) : nullptr;
+                    q.Dm = sym_op(t.op) ? (const void *)(scr + ts[i].ds) : nullptr;
                     q.Vb = (const double *)(scr + ts[i].vb) + ts[i].voff[l];
                     q.out = t.out;
                     q.n_ao = pl->n_ao;
                     q.emax = emax;
                     q.vz = block_column(pl, l);
                     q.G = pl->geom[l];
-                    (t.op == GPW_OP_MAT ? mats : grads).add(q, np);
+                    (t.op == GPW_OP_MAT       ? mats
+                     : t.op == GPW_OP_GRAD    ? grads
+                     : t.op == GPW_OP_MAT_TAU ? mtaus
+                                              : gtaus)
+                        .add(q, np);
                 }
             }
         }
@@ -1684,6 +2065,19 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
             }, true);
             grads.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
                 hipLaunchKernelGGL((k_grad<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
+            }, true);
+            tpacks.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_pack_tau<T, LA, LB>), dim3(g), dim3(256), 0, st, tb);
+            }, false);
+            using TS = TauSplit<LA + LB + 2>;
+            taus.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_tau<LA, LB, TS::npass, TS::wpe, T>), dim3(g), dim3(64), 0, st, tb);
+            }, true);
+            mtaus.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_mat_tau<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
+            }, true);
+            gtaus.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+                hipLaunchKernelGGL((k_grad_tau<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
             }, true);
         });
     }

@@ -641,6 +641,15 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         const double ft = 8.0 * (L + 2) * (L + 1) * L / 6.0 + 32.0 * (L + 1) * L / 2.0 + 16.0 + 64.0 * (2 * L + 3);
         I.flops_rho_exec += rho_tensor(la, lb) ? ft * (double)ninc : f1 * blkpts;
         I.flops_mat_exec += (mat_tensor(la, lb) ? 2.0 * L + 3.0 : f1) * blkpts;
+        // the same counts two and three degrees higher for the kinetic energy
+        // density terms, and one degree higher for the gradient's moments
+        const double L2 = L + 2.0;
+        I.flops_tau_exec +=
+            (8.0 * (L2 + 2) * (L2 + 1) * L2 / 6.0 + 32.0 * (L2 + 1) * L2 / 2.0 + 16.0 + 64.0 * (2 * L2 + 3)) *
+            (double)ninc;
+        I.flops_grad_exec += (2.0 * (L + 1) + 3.0) * blkpts;
+        I.flops_mat_tau_exec += (2.0 * (L + 2) + 3.0) * blkpts;
+        I.flops_grad_tau_exec += (2.0 * (L + 3) + 3.0) * blkpts;
     }
 
     return hipSuccess;

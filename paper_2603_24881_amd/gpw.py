@@ -56,6 +56,26 @@ class GPW:
         _lib.gpw_eval_grad(self.plan, D, [v.contiguous() for v in V], out, stream)
         return out
 
+    def tau(self, D, out=None, stream=None):
+        """Kinetic energy density 1/2 sum D grad phi . grad phi on every level."""
+        out = self.new_grids() if out is None else out
+        _lib.gpw_eval_tau(self.plan, D, out, stream)
+        return out
+
+    def mat_tau(self, Vtau, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.n_ao, self.n_ao), dtype=torch.float64, device=self._dev())
+        _lib.gpw_eval_mat_tau(self.plan, [v.contiguous() for v in Vtau], out, stream)
+        return out
+
+    def grad_tau(self, D, Vtau, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.natm, 3), dtype=torch.float64, device=self._dev())
+        _lib.gpw_eval_grad_tau(self.plan, D, [v.contiguous() for v in Vtau], out, stream)
+        return out
+
     def poisson(self):
         """Multigrid transfer + Poisson solver for this plan's levels, on its device."""
         from .poisson import MultigridPoisson

@@ -79,6 +79,9 @@ def test_null_arguments():
     assert lib.gpw_eval_mat(None, None, None, None) == 1
     assert lib.gpw_eval_grad(None, None, None, None, None) == 1
     assert lib.gpw_eval_mat_noalloc(None, None, None, None) == 1
+    assert lib.gpw_eval_tau(None, None, None, None) == 1
+    assert lib.gpw_eval_mat_tau(None, None, None, None) == 1
+    assert lib.gpw_eval_grad_tau(None, None, None, None, None) == 1
     assert lib.gpw_eval_batch(None, -1, None) == 1
     assert lib.gpw_eval_batch(None, 0, None) == 0
     one = (_lib.gpw_task * 1)()
