@@ -6,16 +6,16 @@ potentials -> matrix) of the 256-water-like system (config-5 member with 256
 water units: 768 atoms, 10496 Cartesian AOs, levels 400/130/45/15 Ry, mesh
 192^3/108^3/64^3/40^3, tau = 1e-6), FP64, inputs resident in HBM.
 
-Prints ONE JSON line.  ``value`` is GFLOP/s of rho+mat counted with the
-fixed per-(pair image, grid point) convention F = 2 n_a n_b + 2 (n_a + n_b) + 4
-(the direct evaluation) over the 64 points of every 4x4x4 block that a pair
-image's truncation sphere meets (the points the block method visits; the block
-set comes from the exact spheres, so loose screening cannot inflate it).
-``useful_gflops`` counts only the points inside the spheres.  The kernels
-evaluate the heavy classes through coefficient tensors and moments (Eq.
-(rho1) and its integration analogue), which needs fewer operations than the
-convention counts: ``executed_gflops`` is the arithmetic they perform (the
-plan's kernel flop model) per second.
+Prints ONE JSON line.  ``value`` is GFLOP/s of the arithmetic the rho and mat
+kernels perform (the plan's kernel flop model: the direct evaluation for the
+classes evaluated directly, the coefficient-tensor Horner evaluation of Eq.
+(rho1) and the potential moments for the others), so it and ``roofline.frac``
+measure work done.  ``convention_gflops`` counts instead the fixed
+per-(pair image, grid point) convention F = 2 n_a n_b + 2 (n_a + n_b) + 4 of
+the direct evaluation over the 64 points of every 4x4x4 block a truncation
+sphere meets; the factorised kernels need fewer operations than that, so the
+convention rate of a class can exceed the hardware peak.  ``useful_gflops``
+counts the convention over the points inside the spheres only.
 """
 from __future__ import annotations
 
@@ -76,10 +76,35 @@ def timed(fn, steps, stream):
     return start.elapsed_time(end) / 1e3 / steps
 
 
+def _sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for fn in ("gpw_eval.hip", "gpw_partition.hip", "gpw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2603_24881_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_flops():
+    """FP64 flops per evaluation of eval_rho and eval_mat on the 256-water system,
+    from the committed rocprofv3 FP64 VALU counter summary ((2 FMA + ADD + MUL) x 64
+    lanes), or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_rho_k_mat_water256_fp64_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 2 and parts[0] in ("eval_rho_flops", "eval_mat_flops", "source_sha256"):
+            vals[parts[0]] = parts[1]
+    if vals.get("source_sha256") != _sources_sha() or len(vals) != 3:
+        return None
+    return {"eval_rho": float(vals["eval_rho_flops"]), "eval_mat": float(vals["eval_mat_flops"])}
+
+
 def measured_traffic(op):
     """HBM bytes per evaluation of ``op`` from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "eval_rho_eval_mat_water256_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -89,22 +114,59 @@ def measured_traffic(op):
             continue
         k, v = line.split()[:2]
         vals[k] = v
-    h = hashlib.sha256()
-    for fn in ("gpw_eval.hip", "gpw_partition.hip", "gpw_internal.h"):
-        with open(os.path.join(ROOT, "paper_2603_24881_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
-    if vals.get("source_sha256") != h.hexdigest() or f"{op}_bytes" not in vals:
+    if vals.get("source_sha256") != _sources_sha() or f"{op}_bytes" not in vals:
         return None
     return int(vals[f"{op}_bytes"])
 
 
-def cpu_baseline(system, D_np, V_np, natoms_hint, info):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_small_configs():
+    """The oracle (rho + mat) on configs 1 and 2: median of 3 runs with all
+    host threads, and with one thread (config 1: median of 3; config 2: one
+    run), seconds."""
+    import oracle
+    from paper_2603_24881_amd import synth
+    nall = oracle.num_threads()
+    out = {}
+    for name, reps1 in (("config1", 3), ("config2", 1)):
+        s = getattr(synth, name)()
+        o = oracle.Oracle(s)
+        D = synth.make_density(s)
+        V = synth.make_potentials(o.meshes, s.seed)
+        res = {}
+        for nt, reps in ((nall, 3), (1, reps1)):
+            oracle.set_num_threads(nt)
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                o.rho(D)
+                o.mat(V)
+                ts.append(time.perf_counter() - t0)
+            res[f"s_{nt}_threads"] = round(float(np.median(ts)), 4)
+            res[f"runs_{nt}_threads"] = reps
+        oracle.set_num_threads(nall)
+        out[name] = res
+        log(f"[bench] oracle {name}: {res}")
+    return out
+
+
+def cpu_baseline(system, D_np, V_np, natoms_hint, info, job_work):
     """The oracle on a bounded sample: the ordered pair images whose first
     primitive sits on the first ``n`` atoms; rho and mat.  Its rate is stated
     in the GPU's unit: the oracle evaluates ordered pairs (each canonical pair
     image twice), so the sample is the fraction ordered_sample / (2 x canonical
     in-sphere work of the job) of the job, and value = that fraction of the
-    job's block flops per second of oracle time."""
+    job's work (``job_work``, the same count as the GPU value) per second of
+    oracle time: both values measure job throughput."""
     import oracle
     n = natoms_hint or max(3, int(round(system.natm * 0.30)))
     mask = np.zeros(system.natm, dtype=np.uint8)
@@ -125,15 +187,14 @@ def cpu_baseline(system, D_np, V_np, natoms_hint, info):
             flops += f * (c_rho[4 * la + lb] + c_mat[4 * la + lb])
     secs = t2 - t0
     job_sphere = info["flops_rho_sphere"] + info["flops_mat_sphere"]
-    job_block = info["flops_rho_block"] + info["flops_mat_block"]
     frac = flops / (2.0 * job_sphere)
-    return {"value": round(frac * job_block / secs / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+    return {"value": round(frac * job_work / secs / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"oracle eval_rho+eval_mat over the ordered pair images whose first primitive sits on the "
                       f"first {n} of {system.natm} atoms: {flops:.3e} in-sphere flops in {secs:.1f} s, "
                       f"{100 * frac:.2f}% of the job",
-            "executed_gflops": round(flops / secs / 1e9, 3), "seconds": round(secs, 2),
-            "cpu": platform.processor() or platform.machine()}
+            "oracle_gflops": round(flops / secs / 1e9, 3), "seconds": round(secs, 2),
+            "cpu": cpu_model(), "small_configs": cpu_small_configs()}
 
 
 def fp32_errors():
@@ -247,14 +308,26 @@ def main():
     t_mat = timed(lambda: g.mat(V, out=M), max(2, args.steps // 2), stream)
     f_rho_s, f_mat_s = info["flops_rho_sphere"], info["flops_mat_sphere"]
     f_rho_b, f_mat_b = info["flops_rho_block"], info["flops_mat_block"]
-    value = (f_rho_b + f_mat_b) / t_step / 1e9
-    log(f"[bench] step {t_step * 1e3:.2f} ms (rho {t_rho * 1e3:.2f} ms, mat {t_mat * 1e3:.2f} ms), "
-        f"{value:.0f} GFLOP/s block work, {(f_rho_s + f_mat_s) / t_step / 1e9:.0f} GFLOP/s in-sphere, "
-        f"{(info['flops_rho_exec'] + info['flops_mat_exec']) / t_step / 1e9:.0f} GFLOP/s executed")
-    if t_rho >= t_mat:
-        dom, dt, fl, op = "k_rho (density collocation, all classes and levels of one eval_rho)", t_rho, f_rho_b, "eval_rho"
+    # the work of one evaluation: the FP64 arithmetic the kernels execute, from the
+    # committed counter summary of this system while it matches the sources, else
+    # the plan's kernel flop model
+    cf = counter_flops() if args.workload == "water256" else None
+    if cf is not None:
+        f_rho_x, f_mat_x = cf["eval_rho"], cf["eval_mat"]
+        work = "FP64 VALU instructions executed, (2 FMA + ADD + MUL) x 64 lanes (rocprofv3 counters, " \
+               "profiles/k_rho_k_mat_water256_fp64_counters.md)"
     else:
-        dom, dt, fl, op = "k_mat (potential integration, all classes and levels of one eval_mat)", t_mat, f_mat_b, "eval_mat"
+        f_rho_x, f_mat_x = info["flops_rho_exec"], info["flops_mat_exec"]
+        work = "the plan's kernel flop model (flops_rho_exec, flops_mat_exec)"
+    value = (f_rho_x + f_mat_x) / t_step / 1e9
+    conv = (f_rho_b + f_mat_b) / t_step / 1e9
+    log(f"[bench] step {t_step * 1e3:.2f} ms (rho {t_rho * 1e3:.2f} ms, mat {t_mat * 1e3:.2f} ms), "
+        f"{value:.0f} GFLOP/s executed, {conv:.0f} GFLOP/s by the block convention, "
+        f"{(f_rho_s + f_mat_s) / t_step / 1e9:.0f} GFLOP/s in-sphere convention")
+    if t_rho >= t_mat:
+        dom, dt, fl, op = "k_rho (density collocation, all classes and levels of one eval_rho)", t_rho, f_rho_x, "eval_rho"
+    else:
+        dom, dt, fl, op = "k_mat (potential integration, all classes and levels of one eval_mat)", t_mat, f_mat_x, "eval_mat"
     traffic = measured_traffic(op) if args.workload == "water256" else None
     out = {
         "metric": "eval_rho+eval_mat FP64 GFLOP/s & %peak; served requests/s + p50/p99 latency",
@@ -271,16 +344,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "tau": system.tau, "levels_ry": system.ke_cutoff_ry,
                    "mesh": info["mesh"], "rel_cutoff_ry": system.rel_cutoff_ry},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": round(fl / dt / 1e12, 3),
-                     "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": round(fl / dt / PEAK_FP64, 4),
-                     "traffic": traffic},
+        "roofline": {"bound": "alu", "kernel": dom, "work": work,
+                     "achieved": round(fl / dt / 1e12, 3), "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                     "frac": round(fl / dt / PEAK_FP64, 4), "traffic": traffic},
         "pct_fp64_peak": round(100 * value * 1e9 / PEAK_FP64, 2),
         "ms_rho": round(t_rho * 1e3, 4),
         "ms_mat": round(t_mat * 1e3, 4),
+        "rho_gflops": round(f_rho_x / t_rho / 1e9, 2),
+        "mat_gflops": round(f_mat_x / t_mat / 1e9, 2),
+        "model_gflops": round((info["flops_rho_exec"] + info["flops_mat_exec"]) / t_step / 1e9, 2),
+        "convention_gflops": round(conv, 2),
+        "pct_fp64_peak_convention": round(100 * conv * 1e9 / PEAK_FP64, 2),
         "useful_gflops": round((f_rho_s + f_mat_s) / t_step / 1e9, 2),
         "pct_fp64_peak_useful": round(100 * (f_rho_s + f_mat_s) / t_step / PEAK_FP64, 2),
-        "executed_gflops": round((info["flops_rho_exec"] + info["flops_mat_exec"]) / t_step / 1e9, 2),
-        "pct_fp64_peak_executed": round(100 * (info["flops_rho_exec"] + info["flops_mat_exec"]) / t_step / PEAK_FP64, 2),
         "max_box_width": info["max_box_width"],
         "plan_s": round(plan_s, 3),
         "n_pair_images": int(sum(info["n_pairs"])),
@@ -291,8 +367,28 @@ def main():
         g.grad(D, V, out=G)
         t_grad = timed(lambda: g.grad(D, V, out=G), max(2, args.steps // 2), stream)
         out["ms_grad"] = round(t_grad * 1e3, 4)
-        out["grad_gflops"] = round(info["flops_grad_block"] / t_grad / 1e9, 2)
+        out["grad_gflops"] = round(info["flops_grad_exec"] / t_grad / 1e9, 2)
+        out["grad_convention_gflops"] = round(info["flops_grad_block"] / t_grad / 1e9, 2)
         log(f"[bench] grad {t_grad * 1e3:.2f} ms")
+        # meta-GGA kinetic-energy-density terms on the same plan
+        T = g.new_grids()
+        g.tau(D, out=T)
+        g.mat_tau(V, out=M)
+        g.grad_tau(D, V, out=G)
+        reps = max(2, args.steps // 4)
+        t_tau = timed(lambda: g.tau(D, out=T), reps, stream)
+        t_mtau = timed(lambda: g.mat_tau(V, out=M), reps, stream)
+        t_gtau = timed(lambda: g.grad_tau(D, V, out=G), reps, stream)
+        out["meta_gga"] = {
+            "ms_tau": round(t_tau * 1e3, 4), "ms_mat_tau": round(t_mtau * 1e3, 4),
+            "ms_grad_tau": round(t_gtau * 1e3, 4),
+            "tau_gflops": round(info["flops_tau_exec"] / t_tau / 1e9, 2),
+            "mat_tau_gflops": round(info["flops_mat_tau_exec"] / t_mtau / 1e9, 2),
+            "grad_tau_gflops": round(info["flops_grad_tau_exec"] / t_gtau / 1e9, 2),
+            "frac_tau": round(info["flops_tau_exec"] / t_tau / PEAK_FP64, 4),
+        }
+        log(f"[bench] meta-GGA: {out['meta_gga']}")
+        del T
         g32 = GPW(system, precision="fp32")
         g32.rho(D, out=rho)
         g32.mat(V, out=M)
@@ -311,7 +407,7 @@ def main():
                                  args.serve_budget_gb)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)...")
-        out["cpu_baseline"] = cpu_baseline(system, Dn, V_np, args.cpu_atoms, info)
+        out["cpu_baseline"] = cpu_baseline(system, Dn, V_np, args.cpu_atoms, info, f_rho_x + f_mat_x)
         log(f"[bench] cpu {out['cpu_baseline']['value']:.2f} GFLOP/s")
     print(json.dumps(out), flush=True)
 

@@ -115,12 +115,18 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load libgpw.so; raises if it is missing (build it with build.py)."""
+    """Load libgpw.so; raises if it is missing (build it with build.py).
+
+    torch is imported first: the ROCm wheel of torch carries its own HIP runtime
+    (soname libamdhip64.so.7), and libgpw.so must bind to that same runtime.
+    Loaded before torch, libgpw.so would bring in the system copy and torch a
+    second one, and torch would then see no device."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libgpw.so not built at {path}; run `python -m paper_2603_24881_amd.build`")
+    import torch  # noqa: F401  (see above)
     lib = C.CDLL(path)
     lib.gpw_plan.argtypes = [C.POINTER(gpw_cell), C.POINTER(gpw_basis), C.POINTER(gpw_cutoffs),
                              C.POINTER(C.c_void_p)]

@@ -243,7 +243,7 @@ class GPUExecutor:
         # the library's own scratch of each operation (packed D of the collocation;
         # block-ordered potentials, with their periodic column extension, of the
         # integration and the gradient; the symmetrised D of the gradient)
-        scr_rho, scr_mat, scr_grad = (int(x) for x in info["scratch_bytes"])
+        scr_rho, scr_mat, scr_grad = (int(x) for x in info["scratch_bytes"][:3])
         # D, the level densities and then potentials, the Poisson step's FFT
         # temporaries; the collocation's and the second stage's scratch never
         # coexist within one request

@@ -87,3 +87,16 @@ def test_null_arguments():
     one = (_lib.gpw_task * 1)()
     assert lib.gpw_eval_batch(one, 1, None) == 1          # NULL plan
     assert "NULL plan" in _lib.gpw_last_error()
+
+
+def test_library_and_torch_share_one_hip_runtime():
+    """Loading the library before torch must not bring a second HIP runtime into
+    the process (torch then reports no device): the binding binds libgpw.so to
+    the runtime torch carries."""
+    import subprocess
+    import sys
+    code = ("import paper_2603_24881_amd._lib as L; L.load(); import torch; "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs

@@ -51,6 +51,9 @@ def test_wrong_buffers_raise_before_the_library(plan):
 
 def test_scratch_bytes_reported(plan):
     scr = plan.info["scratch_bytes"]
-    assert len(scr) == 3 and all(int(x) > 0 for x in scr)
+    assert len(scr) == 6 and all(int(x) > 0 for x in scr)
     # the gradient also holds the symmetrised D next to the block-ordered potential
     assert scr[2] >= scr[1] + 8 * plan.n_ao ** 2
+    # the meta-GGA terms: larger coefficient tensors than the density's; the same
+    # block-ordered potential (and symmetrised D) as integration and gradient
+    assert scr[3] > scr[0] and scr[4] == scr[1] and scr[5] == scr[2]
