@@ -79,9 +79,11 @@ def timed(fn, steps, stream):
 def _sources_sha():
     import hashlib
     h = hashlib.sha256()
-    for fn in ("gpw_eval.hip", "gpw_partition.hip", "gpw_internal.h"):
-        with open(os.path.join(ROOT, "paper_2603_24881_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
+    csrc = os.path.join(ROOT, "paper_2603_24881_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(f.read())
     return h.hexdigest()
 
 

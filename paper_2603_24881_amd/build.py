@@ -10,15 +10,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpw.so")
 SOURCES = ["gpw_api.hip", "gpw_partition.hip", "gpw_eval.hip"]
+# the class kernels: gpw_class.hip once per (l_a, l_b) class
+NCLASS = 10
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
 
-def _compile(src: str, objdir: str) -> str:
-    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job, objdir: str) -> str:
+    src, defs = job if isinstance(job, tuple) else (job, [])
+    tag = "".join("_" + d.split("=")[1] for d in defs)
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + tag + ".o")
+    cmd = [HIPCC, *FLAGS, *("-D" + d for d in defs), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -30,9 +34,11 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link libgpw.so next to this file."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    srcs = list(SOURCES)
-    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, objdir), srcs))
+    # the class objects first: they take longest
+    jobs = [("gpw_class.hip", [f"GPW_CLS={c}"]) for c in range(NCLASS)] + list(SOURCES)
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda j: _compile(j, objdir), jobs))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

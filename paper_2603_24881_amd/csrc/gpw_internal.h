@@ -21,8 +21,15 @@ __host__ __device__ inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 __host__ __device__ constexpr int ncart_c(int l) { return (l + 1) * (l + 2) / 2; }
 // class index of (la, lb), la >= lb: ss ps pp ds dp dd fs fp fd ff
 __host__ __device__ inline int cls_of(int la, int lb) { return la * (la + 1) / 2 + lb; }
-__host__ __device__ inline int cls_la(int c) { return c >= 6 ? 3 : c >= 3 ? 2 : c >= 1 ? 1 : 0; }
-__host__ __device__ inline int cls_lb(int c) { int la = cls_la(c); return c - la * (la + 1) / 2; }
+__host__ __device__ constexpr int cls_la_c(int c)
+{
+    int la = 0;
+    while ((la + 1) * (la + 2) / 2 <= c) ++la;
+    return la;
+}
+__host__ __device__ constexpr int cls_lb_c(int c) { return c - cls_la_c(c) * (cls_la_c(c) + 1) / 2; }
+__host__ __device__ inline int cls_la(int c) { return cls_la_c(c); }
+__host__ __device__ inline int cls_lb(int c) { return cls_lb_c(c); }
 
 // Monomials (x-A_x)^lx (y-A_y)^ly (z-A_z)^lz of total degree <= L.
 __host__ __device__ constexpr int ntab(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
