@@ -182,11 +182,11 @@ def cpu_baseline(system, D_np, V_np, natoms_hint, info, job_work):
     t2 = time.perf_counter()
     c_mat = o.counts.copy()
     flops = 0.0
-    for la in range(4):
-        for lb in range(4):
+    for la in range(5):
+        for lb in range(5):
             na, nb = (la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2
             f = 2 * na * nb + 2 * (na + nb) + 4
-            flops += f * (c_rho[4 * la + lb] + c_mat[4 * la + lb])
+            flops += f * (c_rho[5 * la + lb] + c_mat[5 * la + lb])
     secs = t2 - t0
     job_sphere = info["flops_rho_sphere"] + info["flops_mat_sphere"]
     frac = flops / (2.0 * job_sphere)

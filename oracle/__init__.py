@@ -16,6 +16,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+# points visited per (l_a, l_b) of the ordered pairs, index 5 l_a + l_b (l <= 4)
+NCOUNT = 25
 _SRC = os.path.join(_HERE, "gpw_oracle.c")
 _LIB = os.path.join(_HERE, "libgpw_oracle.so")
 
@@ -141,7 +143,7 @@ class Oracle:
                         if self.atom_mask is not None else None)
         st.mask_either = 1 if mask_either else 0
         self._st = st
-        self.counts = np.zeros(16, dtype=np.int64)
+        self.counts = np.zeros(NCOUNT, dtype=np.int64)
 
     # -- layout helpers ---------------------------------------------------
     @property
@@ -168,7 +170,7 @@ class Oracle:
         D = np.ascontiguousarray(D, dtype=np.float64)
         total = sum(m[0] * m[1] * m[2] for m in self.meshes)
         out = np.zeros(total, dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_rho(C.byref(self._st), _dp(D), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_rho: allocation failed")
         self.counts = cnt
@@ -178,7 +180,7 @@ class Oracle:
         D = np.ascontiguousarray(D, dtype=np.float64)
         idx = np.ascontiguousarray(flat_idx, dtype=np.int64)
         out = np.zeros(len(idx), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_rho_points(C.byref(self._st), _dp(D), C.c_int(level), C.c_long(len(idx)),
                                      _lp(idx), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_rho_points: allocation failed")
@@ -188,7 +190,7 @@ class Oracle:
     def mat(self, V):
         v = self._concat(V)
         out = np.zeros((self.n_ao, self.n_ao), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_mat(C.byref(self._st), _dp(v), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_mat: allocation failed")
         self.counts = cnt
@@ -209,7 +211,7 @@ class Oracle:
             sizes.append((pos, na, nb))
             pos += na * nb
         out = np.zeros(max(pos, 1), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_mat_blocks(C.byref(self._st), _dp(v), _lp(slot), C.c_long(max(pos, 1)),
                                      _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_mat_blocks: allocation failed")
@@ -220,7 +222,7 @@ class Oracle:
         D = np.ascontiguousarray(D, dtype=np.float64)
         v = self._concat(V)
         out = np.zeros((self.s.natm, 3), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_grad(C.byref(self._st), _dp(D), _dp(v), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_grad: allocation failed")
         self.counts = cnt
@@ -232,7 +234,7 @@ class Oracle:
         D = np.ascontiguousarray(D, dtype=np.float64)
         total = sum(m[0] * m[1] * m[2] for m in self.meshes)
         out = np.zeros(total, dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_tau(C.byref(self._st), _dp(D), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_tau: allocation failed")
         self.counts = cnt
@@ -242,7 +244,7 @@ class Oracle:
         D = np.ascontiguousarray(D, dtype=np.float64)
         idx = np.ascontiguousarray(flat_idx, dtype=np.int64)
         out = np.zeros(len(idx), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_tau_points(C.byref(self._st), _dp(D), C.c_int(level), C.c_long(len(idx)),
                                      _lp(idx), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_tau_points: allocation failed")
@@ -253,7 +255,7 @@ class Oracle:
         """The kinetic-energy-density term of the matrix for level potentials vtau."""
         v = self._concat(V)
         out = np.zeros((self.n_ao, self.n_ao), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_mat_tau(C.byref(self._st), _dp(v), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_mat_tau: allocation failed")
         self.counts = cnt
@@ -273,7 +275,7 @@ class Oracle:
             sizes.append((pos, na, nb))
             pos += na * nb
         out = np.zeros(max(pos, 1), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_mat_tau_blocks(C.byref(self._st), _dp(v), _lp(slot), C.c_long(max(pos, 1)),
                                          _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_mat_tau_blocks: allocation failed")
@@ -285,7 +287,7 @@ class Oracle:
         D = np.ascontiguousarray(D, dtype=np.float64)
         v = self._concat(V)
         out = np.zeros((self.s.natm, 3), dtype=np.float64)
-        cnt = np.zeros(16, dtype=np.int64)
+        cnt = np.zeros(NCOUNT, dtype=np.int64)
         if _load().oracle_grad_tau(C.byref(self._st), _dp(D), _dp(v), _dp(out), _lp(cnt)) != 0:
             raise MemoryError("oracle_grad_tau: allocation failed")
         self.counts = cnt

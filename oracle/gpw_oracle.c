@@ -72,7 +72,9 @@
 #include <omp.h>
 #endif
 
-#define OR_MAXL 3
+#define OR_MAXL 4                  /* up to g shells */
+#define OR_NCART 15                /* Cartesian components of a g shell */
+#define OR_NCNT 25                 /* per-(l_a, l_b) counters, index 5 l_a + l_b */
 
 typedef struct {
     double cell[3];
@@ -319,7 +321,7 @@ typedef struct {
     /* requested matrix blocks (mat only): shell-pair -> offset or -1 */
     const long *sp_slot;
     /* evaluation counters per (la, lb) and thread */
-    long *counts;              /* nthreads * 16 */
+    long *counts;              /* nthreads * OR_NCNT */
 } octx;
 
 static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
@@ -357,7 +359,7 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
         tab1d(p->A[d], p->aa, h[d], lo[d], n[d], ea, ga[d]);
         tab1d(p->B[d], p->ab, h[d], lo[d], n[d], eb, gb[d]);
     }
-    int ax[10][3], bx[10][3];
+    int ax[OR_NCART][3], bx[OR_NCART][3];
     for (int m = 0; m < na; ++m) cart_exps(la, m, &ax[m][0], &ax[m][1], &ax[m][2]);
     for (int m = 0; m < nb; ++m) cart_exps(lb, m, &bx[m][0], &bx[m][1], &bx[m][2]);
     const int mu0 = c->ao_off[p->sa], nu0 = c->ao_off[p->sb];
@@ -398,7 +400,7 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
                     if (dx * dx + dy * dy + dz * dz > R2) continue;
                     ++nvis;
                     long wflat = (lmod(ux, N[0]) * N[1] + lmod(uy, N[1])) * N[2] + lmod(uz, N[2]);
-                    double Ga[10], Gb[10];
+                    double Ga[OR_NCART], Gb[OR_NCART];
                     for (int m = 0; m < na; ++m)
                         Ga[m] = ga[0][ax[m][0] * n[0] + tx] * ga[1][ax[m][1] * n[1] + ty] *
                                 ga[2][ax[m][2] * n[2] + tz];
@@ -407,7 +409,7 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
                                 gb[2][bx[m][2] * n[2] + tz];
                     if (c->mode >= MODE_TAU) {
                         long tt[3] = {tx, ty, tz};
-                        double Da[10][3], Db[10][3];   /* grad G along each axis */
+                        double Da[OR_NCART][3], Db[OR_NCART][3];   /* grad G along each axis */
                         for (int m = 0; m < na; ++m)
                             for (int d = 0; d < 3; ++d) Da[m][d] = cart_d1(ga, n, tt, ax[m], p->aa, d);
                         for (int m = 0; m < nb; ++m)
@@ -522,7 +524,7 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
         }
     }
 done:
-    c->counts[tid * 16 + 4 * la + lb] += nvis;
+    c->counts[tid * OR_NCNT + 5 * la + lb] += nvis;
     for (int d = 0; d < 3; ++d) { free(ga[d]); free(gb[d]); }
 }
 
@@ -548,7 +550,7 @@ static void setup_ctx(const osys *s, octx *c, int mode)
     for (int i = 0; i < s->nlevels; ++i)
         c->lvl_off[i + 1] = c->lvl_off[i] + (long)s->mesh[3 * i] * s->mesh[3 * i + 1] * s->mesh[3 * i + 2];
     c->nthreads = n_threads();
-    c->counts = (long *)calloc((size_t)c->nthreads * 16, sizeof(long));
+    c->counts = (long *)calloc((size_t)c->nthreads * OR_NCNT, sizeof(long));
 }
 
 static int alloc_bufs(octx *c, long len)
@@ -570,9 +572,9 @@ static void finish(octx *c, double *out, long *counts_out)
             for (long i = 0; i < c->tlen; ++i) out[i] += c->tbuf[t][i];
     }
     if (counts_out)
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < OR_NCNT; ++k) {
             long acc = 0;
-            for (int t = 0; t < c->nthreads; ++t) acc += c->counts[t * 16 + k];
+            for (int t = 0; t < c->nthreads; ++t) acc += c->counts[t * OR_NCNT + k];
             counts_out[k] = acc;
         }
     if (c->tbuf)

@@ -30,7 +30,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # Cartesian component counts per angular momentum.
-NCART = (1, 3, 6, 10)
+NCART = (1, 3, 6, 10, 15)
 
 # Water geometry: O-H bond length (bohr) and H-O-H angle (degrees).
 OH_BOND = 1.81
