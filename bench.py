@@ -285,7 +285,7 @@ def main():
     info = g.info
     log(f"[bench] plan {plan_s:.2f} s, pairs {sum(info['n_pairs'])}, incidences {sum(info['n_incidences'])}, "
         f"mesh {info['mesh']}, device bytes {info['device_bytes'] / 1e9:.2f} GB")
-    names = ["ss", "ps", "pp", "ds", "dp", "dd", "fs", "fp", "fd", "ff"]
+    names = ["ss", "ps", "pp", "ds", "dp", "dd", "fs", "fp", "fd", "ff", "gs", "gp", "gd", "gf", "gg"]
     log("[bench] per class: " + ", ".join(f"{n}: {p} pairs / {i} blocks" for n, p, i in
                                           zip(names, info["n_pairs_class"], info["n_incidences_class"])))
     C = synth.draw_orbitals(system)

@@ -22,7 +22,7 @@
  * Units: bohr, bohr^-2 for exponents, Rydberg for plane-wave cutoffs.
  * Cell: orthorhombic; lattice vectors are the rows of a[3][3] and must be
  *   diagonal (non-orthogonal cells return GPW_EUNSUPPORTED).
- * Basis: contracted Cartesian shells, l = 0..3.  exps/coefs are the primitive
+ * Basis: contracted Cartesian shells, l = 0..4.  exps/coefs are the primitive
  *   exponents and raw coefficients: a contracted AO is
  *   sum_k coefs[k] (x-Ax)^i (y-Ay)^j (z-Az)^k exp(-exps[k] |r-A|^2)
  *   (un-normalised Cartesian primitives, Sec. III.A, Eq. (gx)).
@@ -70,11 +70,11 @@ extern "C" {
 #endif
 
 #define GPW_MAX_LEVELS 8
-#define GPW_NCLASS 10   /* (l_a, l_b) with 3 >= l_a >= l_b >= 0 */
+#define GPW_NCLASS 15   /* (l_a, l_b) with 4 >= l_a >= l_b >= 0 */
 
 typedef enum {
     GPW_OK = 0,
-    GPW_EINVAL = 1,        /* bad argument (NULL pointer, l > 3, exponent <= 0, ...) */
+    GPW_EINVAL = 1,        /* bad argument (NULL pointer, l < 0, exponent <= 0, ...) */
     GPW_EUNSUPPORTED = 2,  /* valid but not implemented (non-orthogonal cell, g shells) */
     GPW_ENOMEM = 3,        /* device allocation failed */
     GPW_EDEVICE = 4,       /* HIP runtime error or device fault */
@@ -94,7 +94,7 @@ typedef struct {
     const double *coords;       /* natm*3, any position (not wrapped) */
     int nshell;
     const int *shell_atom;      /* nshell, atom index of each shell */
-    const int *shell_l;         /* nshell, 0..3 */
+    const int *shell_l;         /* nshell, 0..4 */
     const int *shell_nprim;     /* nshell, >= 1 */
     const int *shell_prim0;     /* nshell, offset of the shell's primitives */
     const double *exps;         /* primitive exponents, > 0 */
@@ -159,7 +159,7 @@ typedef struct {
  * (Sec. III.B; appendix on GTO screening, Algs. 4 and 5).  All host inputs
  * are copied; the caller may free them on return.  The plan owns its device
  * memory on cut->device.  Synchronous.  Errors: GPW_EINVAL for NULL or invalid
- * arguments, GPW_EUNSUPPORTED for a non-diagonal cell, l > 3, or a truncation
+ * arguments, GPW_EUNSUPPORTED for a non-diagonal cell, l > 4, or a truncation
  * sphere too wide for the kernels (more than 1024 points per axis, more than
  * 127 cell periods, or point tables beyond one workgroup's LDS), GPW_ENOMEM,
  * GPW_EDEVICE. */

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgpw.so")
 
 GPW_MAX_LEVELS = 8
-GPW_NCLASS = 10
+GPW_NCLASS = 15
 GPW_FP64, GPW_FP32 = 0, 1
 GPW_OP_RHO, GPW_OP_MAT, GPW_OP_GRAD, GPW_OP_TAU, GPW_OP_MAT_TAU, GPW_OP_GRAD_TAU = 0, 1, 2, 3, 4, 5
 GRID_OPS = (GPW_OP_RHO, GPW_OP_TAU)

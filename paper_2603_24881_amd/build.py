@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpw.so")
 SOURCES = ["gpw_api.hip", "gpw_partition.hip", "gpw_eval.hip"]
 # the class kernels: gpw_class.hip once per (l_a, l_b) class
-NCLASS = 10
+NCLASS = 15
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -100,7 +100,7 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
     for (int s = 0; s < B.nshell; ++s) {
         if (B.shell_atom[s] < 0 || B.shell_atom[s] >= B.natm) return fail(GPW_EINVAL, "gpw_plan: shell_atom out of range");
         if (B.shell_l[s] < 0) return fail(GPW_EINVAL, "gpw_plan: negative angular momentum");
-        if (B.shell_l[s] > 3) return fail(GPW_EUNSUPPORTED, "gpw_plan: angular momentum above 3 (f) is not supported");
+        if (B.shell_l[s] > 4) return fail(GPW_EUNSUPPORTED, "gpw_plan: angular momentum above 4 (g) is not supported");
         if (B.shell_nprim[s] < 1 || B.shell_prim0[s] < 0) return fail(GPW_EINVAL, "gpw_plan: bad primitive range");
         for (int k = 0; k < B.shell_nprim[s]; ++k) {
             const double e = B.exps[B.shell_prim0[s] + k], c = B.coefs[B.shell_prim0[s] + k];

@@ -1,6 +1,6 @@
 // Launches of the kernels of one (l_a, l_b) class.  This source is compiled
 // once per class, with GPW_CLS set to the class index (ss ps pp ds dp dd fs
-// fp fd ff), so that the templated kernels of the classes compile in
+// fp fd ff gs gp gd gf gg), so that the templated kernels of the classes compile in
 // parallel translation units; launch_class() dispatches to them.
 #include "gpw_kernels.h"
 

@@ -270,12 +270,18 @@ void launch_class_6(const ClassLaunch &);
 void launch_class_7(const ClassLaunch &);
 void launch_class_8(const ClassLaunch &);
 void launch_class_9(const ClassLaunch &);
+void launch_class_10(const ClassLaunch &);
+void launch_class_11(const ClassLaunch &);
+void launch_class_12(const ClassLaunch &);
+void launch_class_13(const ClassLaunch &);
+void launch_class_14(const ClassLaunch &);
 
 void launch_class(int c, const ClassLaunch &cl)
 {
     static void (*const fn[kNCls])(const ClassLaunch &) = {
-        launch_class_0, launch_class_1, launch_class_2, launch_class_3, launch_class_4,
-        launch_class_5, launch_class_6, launch_class_7, launch_class_8, launch_class_9};
+        launch_class_0,  launch_class_1,  launch_class_2,  launch_class_3,  launch_class_4,
+        launch_class_5,  launch_class_6,  launch_class_7,  launch_class_8,  launch_class_9,
+        launch_class_10, launch_class_11, launch_class_12, launch_class_13, launch_class_14};
     fn[c](cl);
 }
 

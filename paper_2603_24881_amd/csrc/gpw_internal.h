@@ -19,7 +19,7 @@ constexpr int kMaxGroups = kMaxLevels * kNCls;   // (level, class) groups
 
 __host__ __device__ inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 __host__ __device__ constexpr int ncart_c(int l) { return (l + 1) * (l + 2) / 2; }
-// class index of (la, lb), la >= lb: ss ps pp ds dp dd fs fp fd ff
+// class index of (la, lb), la >= lb: ss ps pp ds dp dd fs fp fd ff gs gp gd gf gg
 __host__ __device__ inline int cls_of(int la, int lb) { return la * (la + 1) / 2 + lb; }
 __host__ __device__ constexpr int cls_la_c(int c)
 {
@@ -42,7 +42,7 @@ __host__ __device__ constexpr int ntab(int L) { return (L + 1) * (L + 2) * (L + 
 // the 256-water system.
 __host__ __device__ constexpr bool rho_tensor(int la, int lb)
 {
-    return la == 2 || (la == 3 && lb >= 1 && lb <= 2);
+    return la == 2 || (la == 3 && lb >= 1 && lb <= 2) || (la == 4 && lb >= 1);
 }
 // Whether the mat kernel of class (la, lb) accumulates the potential moments
 // of the monomials of r - A one axis at a time and forms the matrix elements

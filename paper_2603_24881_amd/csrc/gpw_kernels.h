@@ -916,6 +916,20 @@ template <> struct RhoSplit<3, 3> {
     static constexpr int npass = 4, wpe = 1, wpe2 = 1;
     static constexpr bool stage = false, two = false, pref = false;
 };
+// g classes: the accumulators share the registers with 15 D values (g|s) or a
+// tensor of 56 to 165 values
+template <> struct RhoSplit<4, 0> {
+    static constexpr int npass = 1, wpe = 1, wpe2 = 1;
+    static constexpr bool stage = false, two = false, pref = false;
+};
+template <> struct RhoSplit<4, 1> {
+    static constexpr int npass = 2, wpe = 1, wpe2 = 1;
+    static constexpr bool stage = false, two = false, pref = false;
+};
+template <int LB> struct RhoSplit<4, LB> {
+    static constexpr int npass = 4, wpe = 1, wpe2 = 1;
+    static constexpr bool stage = false, two = false, pref = false;
+};
 
 // Kinetic energy density: points per pass and waves per SIMD by the degree
 // LT of the coefficient tensor (its ntab(LT) values and the accumulators
@@ -1274,7 +1288,7 @@ struct TensorVisit {
 // finish the sum, and lane 8q applies emit(k, sum) for k = chunk + q.  The
 // eight results of a chunk leave in parallel instead of one lane issuing
 // every atomic.
-constexpr size_t kRedBytes = (8 * 65 + 220) * sizeof(double);   // red[8][65] and up to ntab(9) moments
+constexpr size_t kRedBytes = (8 * 65 + 364) * sizeof(double);   // red[8][65] and up to ntab(11) moments
 template <int K, typename T, typename Emit>
 __device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit &&emit)
 {

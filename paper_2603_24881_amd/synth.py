@@ -46,7 +46,7 @@ class System:
     cell: np.ndarray                  # (3,) orthorhombic side lengths
     coords: np.ndarray                # (natm, 3)
     shell_atom: np.ndarray            # (nshell,) int32
-    shell_l: np.ndarray               # (nshell,) int32, 0..3
+    shell_l: np.ndarray               # (nshell,) int32, 0..4
     shell_nprim: np.ndarray           # (nshell,) int32
     shell_prim0: np.ndarray           # (nshell,) int32 offset into exps/coefs
     exps: np.ndarray                  # (nprim_total,) float64

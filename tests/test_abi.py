@@ -33,7 +33,7 @@ def _basis(l=0, exp=1.0):
 
 
 @pytest.mark.parametrize("bad,status", [
-    (dict(shell_l=[4]), 2),            # g shell: unsupported
+    (dict(shell_l=[5]), 2),            # h shell: unsupported
     (dict(shell_l=[-1]), 1),
     (dict(exps=[0.0]), 1),
     (dict(exps=[-1.0]), 1),

@@ -64,6 +64,19 @@ def test_tiny_spdf_all_classes(mesh):
     assert all(c > 0 for c in info["n_pairs_class"]), info["n_pairs_class"]
 
 
+@pytest.mark.parametrize("mesh", [(20, 24, 28), (13, 11, 9)])
+def test_tiny_spdfg_all_fifteen_classes(mesh):
+    """g shells: all fifteen (l_a, l_b) classes up to (g|g) (coefficient
+    tensors of degree 8, gradient moments of degree 9)."""
+    log(f"tiny spdfg mesh={mesh}")
+    s = tiny.tiny_system(shell_ls=(0, 1, 2, 3, 4), mesh=(mesh,), tau=1e-10, seed=17)
+    o = oracle.Oracle(s)
+    D = tiny.random_density(s.n_ao)
+    V = synth.make_potentials(o.meshes, 23)
+    info = _compare(s, D, V)
+    assert len(info["n_pairs_class"]) == 15 and all(c > 0 for c in info["n_pairs_class"]), info["n_pairs_class"]
+
+
 def test_nonsymmetric_density_and_atoms_outside_cell():
     log("nonsymmetric D, atoms outside the cell")
     s = tiny.tiny_system(shell_ls=(0, 1, 2), natm=3, mesh=((16, 18, 20),), tau=1e-8)

@@ -71,6 +71,15 @@ def test_tiny_spdf_all_classes(mesh):
     assert all(c > 0 for c in info["n_pairs_class"]), info["n_pairs_class"]
 
 
+def test_tiny_spdfg_all_fifteen_classes():
+    """g shells: tau tensors up to degree 10, moments up to degree 11."""
+    log("[tau] tiny spdfg")
+    s = tiny.tiny_system(shell_ls=(0, 1, 2, 3, 4), mesh=((20, 24, 28),), tau=1e-10, seed=17)
+    o = oracle.Oracle(s)
+    info = _compare(s, tiny.random_density(s.n_ao), synth.make_potentials(o.meshes, 23))
+    assert all(c > 0 for c in info["n_pairs_class"]), info["n_pairs_class"]
+
+
 def test_nonsymmetric_density_and_atoms_outside_cell():
     log("[tau] nonsymmetric D, atoms outside the cell")
     s = tiny.tiny_system(shell_ls=(0, 1, 2), natm=3, mesh=((16, 18, 20),), tau=1e-8)
