@@ -1,0 +1,79 @@
+"""CPU oracle of the multigrid Fourier transfer and Poisson solve.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may use it; the library never does.
+
+What it computes (Sec. II: the Hartree potential of Eqs. (vH), (vHG) and the
+multigrid Fourier interpolation between levels), plainly, with full complex
+FFTs of numpy (FP64) and one loop over levels:
+
+  level l: mesh N_l, points r_j = j h_l (h_l = L / N_l), weight w_l = Omega / N_l,
+           plane waves G = 2 pi m / L with integer m, |m_d| < N_{l,d} / 2 (no
+           Nyquist plane), kept when |G|^2 < E_l (cutoff in Ry, |G|^2 in bohr^-2;
+           every such plane wave when the level has no cutoff)
+  rho~(G)  = sum_l mask_l(G) w_l sum_j rho_l(r_j) exp(-i G . r_j)
+  v~(G)    = 4 pi rho~(G) / |G|^2 for G != 0, v~(0) = 0
+  v_l(r_j) = (1 / Omega) sum_G mask_l(G) v~(G) exp(i G . r_j)
+  E_J      = (1 / (2 Omega)) sum_{G != 0} 4 pi |rho~(G)|^2 / |G|^2
+
+The coefficients of all levels live on the plane-wave set of the finest mesh
+(level 0 holds the finest mesh); a level's masked plane wave m lands on the
+fine-grid index m mod N_0.  Orthorhombic cell (side lengths L).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _freqs(n):
+    """Integer frequencies m of an n-point FFT, in numpy's order."""
+    return np.fft.fftfreq(n) * n
+
+
+def level_mask(L, mesh, cutoff_ry):
+    """Boolean mask over a level's FFT grid: no Nyquist plane, |G|^2 < E_l."""
+    m = [_freqs(n) for n in mesh]
+    mx, my, mz = np.meshgrid(*m, indexing="ij")
+    ok = (np.abs(mx) < mesh[0] / 2.0) & (np.abs(my) < mesh[1] / 2.0) & (np.abs(mz) < mesh[2] / 2.0)
+    if cutoff_ry is not None:
+        g2 = ((2 * math.pi * mx / L[0]) ** 2 + (2 * math.pi * my / L[1]) ** 2 +
+              (2 * math.pi * mz / L[2]) ** 2)
+        ok &= g2 < cutoff_ry
+    return ok, (mx, my, mz)
+
+
+def poisson(L, meshes, cutoffs_ry, rho):
+    """(v_l per level, E_J) from the level densities rho_l (C-ordered grids).
+    cutoffs_ry: per level cutoff in Ry, or None for every plane wave."""
+    L = np.asarray(L, dtype=np.float64).reshape(3)
+    vol = float(np.prod(L))
+    fine = tuple(int(x) for x in meshes[0])
+    acc = np.zeros(fine, dtype=np.complex128)
+    masks = []
+    for l, mesh in enumerate(meshes):
+        mesh = tuple(int(x) for x in mesh)
+        ok, (mx, my, mz) = level_mask(L, mesh, None if cutoffs_ry is None else cutoffs_ry[l])
+        w = vol / float(np.prod(mesh))
+        f = np.fft.fftn(np.asarray(rho[l], dtype=np.float64).reshape(mesh)) * w
+        ix = np.mod(mx[ok], fine[0]).astype(np.int64)
+        iy = np.mod(my[ok], fine[1]).astype(np.int64)
+        iz = np.mod(mz[ok], fine[2]).astype(np.int64)
+        np.add.at(acc, (ix, iy, iz), f[ok])
+        masks.append((ok, ix, iy, iz))
+    gx, gy, gz = [2 * math.pi * _freqs(n) / L[d] for d, n in enumerate(fine)]
+    g2 = gx[:, None, None] ** 2 + gy[None, :, None] ** 2 + gz[None, None, :] ** 2
+    coul = np.zeros(fine)
+    coul[g2 > 0] = 4 * math.pi / g2[g2 > 0]
+    vt = acc * coul
+    e_j = float(np.sum(np.abs(acc) ** 2 * coul)) / (2.0 * vol)
+    out = []
+    for l, mesh in enumerate(meshes):
+        mesh = tuple(int(x) for x in mesh)
+        ok, ix, iy, iz = masks[l]
+        buf = np.zeros(mesh, dtype=np.complex128)
+        buf[ok] = vt[ix, iy, iz]
+        # (1 / Omega) sum_G c(G) e^{iGr} = (N_l / Omega) ifftn
+        out.append(np.real(np.fft.ifftn(buf)) * (float(np.prod(mesh)) / vol))
+    return out, e_j

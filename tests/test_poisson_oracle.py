@@ -1,0 +1,103 @@
+"""Pins of the Poisson / multigrid-transfer oracle (oracle/poisson.py) by closed
+forms: the potential and energy of a plane-wave density, the cutoff filter
+between two levels, the Nyquist and cutoff exclusions, and the energy
+identity with its gradient (central differences)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import poisson as op
+
+
+def _grid(L, mesh):
+    ax = [np.arange(n) * (L[d] / n) for d, n in enumerate(mesh)]
+    return np.meshgrid(*ax, indexing="ij")
+
+
+def _wave(L, mesh, m, fn):
+    x, y, z = _grid(L, mesh)
+    g = [2 * math.pi * m[d] / L[d] for d in range(3)]
+    return fn(g[0] * x + g[1] * y + g[2] * z), sum(t * t for t in g)
+
+
+def test_plane_wave_potential_and_energy():
+    """rho = cos(G.r): v = 4 pi / |G|^2 cos(G.r), E_J = pi Omega / |G|^2."""
+    L, mesh = (7.0, 8.0, 9.0), (16, 18, 20)
+    rho, g2 = _wave(L, mesh, (1, 2, -3), np.cos)
+    v, e = op.poisson(L, [mesh], None, [rho])
+    np.testing.assert_allclose(v[0], 4 * math.pi / g2 * rho, atol=1e-12, rtol=0)
+    vol = L[0] * L[1] * L[2]
+    assert abs(e - math.pi * vol / g2) < 1e-10 * e
+
+
+def test_constant_density_is_neutralised():
+    """The G = 0 term is dropped (neutralising background): a constant density
+    has zero potential and energy."""
+    L, mesh = (6.0, 7.0, 8.0), (10, 12, 14)
+    v, e = op.poisson(L, [mesh], None, [np.full(mesh, 3.0)])
+    assert np.abs(v[0]).max() < 1e-12 and abs(e) < 1e-20
+
+
+def test_two_levels_filter_and_combine():
+    """A density split over two levels: plane waves below both cutoffs reach
+    both levels' potentials, one between the cutoffs only the fine level."""
+    L = (10.0, 10.0, 10.0)
+    fine, coarse = (24, 24, 24), (12, 12, 12)
+    E = (40.0, 10.0)
+    a0, ga = _wave(L, fine, (1, 0, 2), np.cos)
+    c0, gc = _wave(L, fine, (5, 3, 4), np.cos)
+    b1, gb = _wave(L, coarse, (0, 2, 1), np.sin)
+    assert ga < E[1] and gb < E[1] and E[1] < gc < E[0]
+    v, e = op.poisson(L, [fine, coarse], E, [a0 + c0, b1])
+    a1, _ = _wave(L, coarse, (1, 0, 2), np.cos)
+    b0, _ = _wave(L, fine, (0, 2, 1), np.sin)
+    k = 4 * math.pi
+    np.testing.assert_allclose(v[0], k / ga * a0 + k / gb * b0 + k / gc * c0, atol=1e-12, rtol=0)
+    np.testing.assert_allclose(v[1], k / ga * a1 + k / gb * b1, atol=1e-12, rtol=0)
+    ref = math.pi * 1000.0 * (1 / ga + 1 / gb + 1 / gc)
+    assert abs(e - ref) < 1e-10 * ref
+
+
+def test_waves_beyond_the_cutoff_or_on_the_nyquist_plane_are_dropped():
+    L = (8.0, 8.0, 8.0)
+    mesh = (16, 16, 16)
+    hi, g_hi = _wave(L, mesh, (4, 3, 0), np.cos)     # |G|^2 above the cutoff
+    nyq, _ = _wave(L, mesh, (8, 0, 0), np.cos)       # the Nyquist plane of axis 0
+    assert g_hi > 12.0
+    v, e = op.poisson(L, [mesh], [12.0], [hi + nyq])
+    assert np.abs(v[0]).max() < 1e-12 and abs(e) < 1e-18
+
+
+def test_energy_identity_and_gradient():
+    """E_J = 1/2 sum_l w_l <v_l, rho_l>; dE_J/drho_l(r_j) = w_l v_l(r_j) by
+    central differences on a few grid values."""
+    L = (9.0, 10.0, 11.0)
+    meshes = [(20, 22, 24), (12, 12, 15), (6, 8, 8)]
+    E = (45.0, 15.0, 4.0)
+    rng = np.random.default_rng(5)
+    rho = [rng.standard_normal(m) for m in meshes]
+    v, e = op.poisson(L, meshes, E, rho)
+    vol = L[0] * L[1] * L[2]
+    w = [vol / float(np.prod(m)) for m in meshes]
+    half = 0.5 * sum(wl * float(np.vdot(vl, r)) for wl, vl, r in zip(w, v, rho))
+    assert abs(e - half) < 1e-11 * abs(e)
+    h = 1e-3
+    for l, idx in ((0, (3, 4, 5)), (1, (7, 0, 2)), (2, (5, 7, 1))):
+        rp = [r.copy() for r in rho]
+        rm = [r.copy() for r in rho]
+        rp[l][idx] += h
+        rm[l][idx] -= h
+        fd = (op.poisson(L, meshes, E, rp)[1] - op.poisson(L, meshes, E, rm)[1]) / (2 * h)
+        assert abs(fd - w[l] * v[l][idx]) < 1e-7 * abs(w[l] * v[l][idx]) + 1e-9
+
+
+def test_nyquist_plane_is_dropped_without_a_cutoff():
+    """A level with no cutoff keeps every plane wave of its mesh but the
+    Nyquist planes: (-1)^j along one axis gives no potential."""
+    L, mesh = (8.0, 9.0, 10.0), (16, 18, 20)
+    for m in ((8, 0, 0), (0, 9, 0), (0, 0, 10)):
+        nyq, _ = _wave(L, mesh, m, np.cos)
+        v, e = op.poisson(L, [mesh], None, [nyq])
+        assert np.abs(v[0]).max() < 1e-12 and abs(e) < 1e-18, m
