@@ -28,8 +28,10 @@ import numpy as np
 
 
 def _freqs(n):
-    """Integer frequencies m of an n-point FFT, in numpy's order."""
-    return np.fft.fftfreq(n) * n
+    """Integer frequencies m of an n-point FFT, in numpy's order: 0, 1, ..., then
+    the negative half (integers, not fftfreq(n) * n, whose rounding would put a
+    plane wave at the wrong fine-grid index)."""
+    return np.concatenate([np.arange(0, (n + 1) // 2), np.arange(-(n // 2), 0)]).astype(np.int64)
 
 
 def level_mask(L, mesh, cutoff_ry):
@@ -57,9 +59,9 @@ def poisson(L, meshes, cutoffs_ry, rho):
         ok, (mx, my, mz) = level_mask(L, mesh, None if cutoffs_ry is None else cutoffs_ry[l])
         w = vol / float(np.prod(mesh))
         f = np.fft.fftn(np.asarray(rho[l], dtype=np.float64).reshape(mesh)) * w
-        ix = np.mod(mx[ok], fine[0]).astype(np.int64)
-        iy = np.mod(my[ok], fine[1]).astype(np.int64)
-        iz = np.mod(mz[ok], fine[2]).astype(np.int64)
+        ix = np.mod(mx[ok], fine[0])
+        iy = np.mod(my[ok], fine[1])
+        iz = np.mod(mz[ok], fine[2])
         np.add.at(acc, (ix, iy, iz), f[ok])
         masks.append((ok, ix, iy, iz))
     gx, gy, gz = [2 * math.pi * _freqs(n) / L[d] for d, n in enumerate(fine)]

@@ -101,3 +101,62 @@ def test_nyquist_plane_is_dropped_without_a_cutoff():
         nyq, _ = _wave(L, mesh, m, np.cos)
         v, e = op.poisson(L, [mesh], None, [nyq])
         assert np.abs(v[0]).max() < 1e-12 and abs(e) < 1e-18, m
+
+
+def _brute_poisson(L, meshes, cuts, rho):
+    """The same definition by explicit sums over integer plane waves m with
+    |m_d| < N_d / 2 for every level (no FFT, no index arithmetic)."""
+    L = np.asarray(L, dtype=np.float64)
+    vol = float(np.prod(L))
+    pts, ms, keep = [], [], []
+    for l, mesh in enumerate(meshes):
+        ax = [np.arange(n) * (L[d] / n) for d, n in enumerate(mesh)]
+        r = np.stack(np.meshgrid(*ax, indexing="ij"), axis=-1).reshape(-1, 3)
+        rng_ = [np.arange(-((n - 1) // 2), (n - 1) // 2 + 1) for n in mesh]
+        m = np.stack(np.meshgrid(*rng_, indexing="ij"), axis=-1).reshape(-1, 3)
+        m = m[np.all(2 * np.abs(m) < np.asarray(mesh), axis=1)]
+        g = 2 * math.pi * m / L
+        g2 = np.sum(g * g, axis=1)
+        if cuts is not None:
+            m, g, g2 = m[g2 < cuts[l]], g[g2 < cuts[l]], g2[g2 < cuts[l]]
+        pts.append(r)
+        ms.append(m)
+        keep.append(g)
+    allm = np.unique(np.concatenate(ms), axis=0)
+    index = {tuple(x): i for i, x in enumerate(allm)}
+    rt = np.zeros(len(allm), dtype=np.complex128)
+    for l, mesh in enumerate(meshes):
+        w = vol / float(np.prod(mesh))
+        ph = np.exp(-1j * pts[l] @ keep[l].T)
+        coef = w * (rho[l].reshape(-1) @ ph)
+        for k, m in enumerate(ms[l]):
+            rt[index[tuple(m)]] += coef[k]
+    ga = 2 * math.pi * allm / L
+    g2a = np.sum(ga * ga, axis=1)
+    coul = np.where(g2a > 0, 4 * math.pi / np.where(g2a > 0, g2a, 1.0), 0.0)
+    vt = rt * coul
+    e = float(np.sum(np.abs(rt) ** 2 * coul)) / (2 * vol)
+    v = []
+    for l, mesh in enumerate(meshes):
+        sel = np.array([index[tuple(m)] for m in ms[l]], dtype=np.int64)
+        ph = np.exp(1j * pts[l] @ keep[l].T)
+        v.append(np.real(ph @ vt[sel]).reshape(mesh) / vol)
+    return v, e
+
+
+def test_matches_explicit_plane_wave_sums_on_meshes_with_factor_three():
+    """Random level data on meshes with factors 3 and 5 and odd sizes, two
+    levels with cutoffs: the oracle equals the explicit sums (pins the integer
+    plane-wave indices of every level on the fine grid)."""
+    L = (7.0, 8.0, 9.0)
+    meshes = [(18, 24, 10), (9, 6, 5)]   # 18, 24: fftfreq(n) * n is 6.999... at m = 7
+    E = (60.0, 6.0)
+    rng = np.random.default_rng(9)
+    rho = [rng.standard_normal(m) for m in meshes]
+    v, e = op.poisson(L, meshes, E, rho)
+    vb, eb = _brute_poisson(L, meshes, E, rho)
+    for a, b in zip(v, vb):
+        assert float(np.abs(a - b).max()) < 1e-11 * float(np.abs(b).max())
+    assert abs(e - eb) < 1e-11 * abs(eb)
+    v1, e1 = op.poisson(L, [(18, 15, 9)], None, [rng.standard_normal((18, 15, 9))])
+    assert np.isfinite(e1)
