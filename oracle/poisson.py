@@ -79,3 +79,78 @@ def poisson(L, meshes, cutoffs_ry, rho):
         # (1 / Omega) sum_G c(G) e^{iGr} = (N_l / Omega) ifftn
         out.append(np.real(np.fft.ifftn(buf)) * (float(np.prod(mesh)) / vol))
     return out, e_j
+
+
+def _fine_coefficients(L, meshes, cutoffs_ry, rho):
+    """rho~ on the finest mesh's plane waves and the level masks / fine indices."""
+    L = np.asarray(L, dtype=np.float64).reshape(3)
+    vol = float(np.prod(L))
+    fine = tuple(int(x) for x in meshes[0])
+    acc = np.zeros(fine, dtype=np.complex128)
+    masks = []
+    for l, mesh in enumerate(meshes):
+        mesh = tuple(int(x) for x in mesh)
+        ok, (mx, my, mz) = level_mask(L, mesh, None if cutoffs_ry is None else cutoffs_ry[l])
+        w = vol / float(np.prod(mesh))
+        ix, iy, iz = np.mod(mx[ok], fine[0]), np.mod(my[ok], fine[1]), np.mod(mz[ok], fine[2])
+        if rho is not None:
+            np.add.at(acc, (ix, iy, iz), np.fft.fftn(np.asarray(rho[l], dtype=np.float64).reshape(mesh))[ok] * w)
+        masks.append((ok, ix, iy, iz))
+    return acc, masks, L, vol, fine
+
+
+def _gvectors(L, fine):
+    return [2 * math.pi * _freqs(n).astype(np.float64) / L[d] for d, n in enumerate(fine)]
+
+
+def fine_density(L, meshes, cutoffs_ry, rho):
+    """The total density and its gradient on the finest mesh by Fourier
+    interpolation (Sec. II: rho~ = sum of the masked level transforms; the GGA
+    density gradient as the inverse transform of i G rho~):
+      rho(r)     = (1 / Omega) sum_G rho~(G) exp(i G.r)
+      d_d rho(r) = (1 / Omega) sum_G i G_d rho~(G) exp(i G.r)."""
+    acc, _, L, vol, fine = _fine_coefficients(L, meshes, cutoffs_ry, rho)
+    n0 = float(np.prod(fine))
+    g = _gvectors(L, fine)
+    shape = [(fine[0], 1, 1), (1, fine[1], 1), (1, 1, fine[2])]
+    rf = np.real(np.fft.ifftn(acc)) * (n0 / vol)
+    grad = [np.real(np.fft.ifftn(1j * g[d].reshape(shape[d]) * acc)) * (n0 / vol) for d in range(3)]
+    return rf, grad
+
+
+def hxc_potential(L, meshes, cutoffs_ry, rho, vxc=None, vxc_grad=None):
+    """Level potentials of the Hartree term plus an exchange-correlation
+    potential given on the finest mesh (Sec. II, Eqs. (vH), (vHG)): with
+    w_0 = Omega / N_0 and F the transform of a fine-grid function,
+      v~(G) = 4 pi rho~(G) / |G|^2 + w_0 F(vxc)(G) - i G . w_0 F(vxc_grad)(G)
+    (the last term is the GGA potential after integration by parts: minus the
+    divergence of the vector potential, evaluated in Fourier space), and
+      v_l(r) = (1 / Omega) sum_G mask_l(G) v~(G) exp(i G.r).
+    Returns (v_l per level, E_J) with E_J from the Hartree term alone."""
+    acc, masks, L, vol, fine = _fine_coefficients(L, meshes, cutoffs_ry, rho)
+    ok0 = masks[0][0]
+    n0 = float(np.prod(fine))
+    w0 = vol / n0
+    g = _gvectors(L, fine)
+    shape = [(fine[0], 1, 1), (1, fine[1], 1), (1, 1, fine[2])]
+    g2 = g[0].reshape(shape[0]) ** 2 + g[1].reshape(shape[1]) ** 2 + g[2].reshape(shape[2]) ** 2
+    coul = np.zeros(fine)
+    coul[g2 > 0] = 4 * math.pi / g2[g2 > 0]
+    vt = acc * coul
+    e_j = float(np.sum(np.abs(acc) ** 2 * coul)) / (2.0 * vol)
+    # the fine-grid potentials enter on level 0's plane waves (every level's mask
+    # lies inside it)
+    if vxc is not None:
+        vt = vt + ok0 * w0 * np.fft.fftn(np.asarray(vxc, dtype=np.float64).reshape(fine))
+    if vxc_grad is not None:
+        for d in range(3):
+            vt = vt - ok0 * 1j * g[d].reshape(shape[d]) * w0 * np.fft.fftn(
+                np.asarray(vxc_grad[d], dtype=np.float64).reshape(fine))
+    out = []
+    for l, mesh in enumerate(meshes):
+        mesh = tuple(int(x) for x in mesh)
+        ok, ix, iy, iz = masks[l]
+        buf = np.zeros(mesh, dtype=np.complex128)
+        buf[ok] = vt[ix, iy, iz]
+        out.append(np.real(np.fft.ifftn(buf)) * (float(np.prod(mesh)) / vol))
+    return out, e_j

@@ -7,6 +7,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import pytest
 
 from oracle import poisson as op
 
@@ -160,3 +161,75 @@ def test_matches_explicit_plane_wave_sums_on_meshes_with_factor_three():
     assert abs(e - eb) < 1e-11 * abs(eb)
     v1, e1 = op.poisson(L, [(18, 15, 9)], None, [rng.standard_normal((18, 15, 9))])
     assert np.isfinite(e1)
+
+
+# ------------------------------------------- fine-grid density, gradient, Hxc
+
+def test_fine_density_and_gradient_of_a_coarse_plane_wave():
+    """A plane wave stored on a coarse level is band limited: its Fourier
+    interpolation to the fine mesh is the same plane wave there, and the
+    gradient is -G sin(G.r) (closed forms)."""
+    L = (9.0, 10.0, 11.0)
+    fine, coarse = (24, 24, 30), (12, 12, 15)
+    b1, gb = _wave(L, coarse, (1, -2, 3), np.cos)
+    rf, grad = op.fine_density(L, [fine, coarse], (60.0, 15.0), [np.zeros(fine), b1])
+    b0, _ = _wave(L, fine, (1, -2, 3), np.cos)
+    s0, _ = _wave(L, fine, (1, -2, 3), np.sin)
+    np.testing.assert_allclose(rf, b0, atol=1e-12)
+    g = [2 * math.pi * m / L[d] for d, m in enumerate((1, -2, 3))]
+    for d in range(3):
+        np.testing.assert_allclose(grad[d], -g[d] * s0, atol=1e-11)
+
+
+def test_hxc_without_density_passes_a_band_limited_xc_potential_through():
+    """rho = 0: level 0 receives the fine-grid vxc itself (a plane wave inside
+    its cutoff), a coarse level the same plane wave on its own mesh when it is
+    below the coarse cutoff; the GGA term of v = (0, sin(G.r), 0) is minus its
+    divergence, -G_y cos(G.r)."""
+    L = (9.0, 10.0, 11.0)
+    fine, coarse = (24, 24, 30), (12, 12, 15)
+    E = (60.0, 15.0)
+    c0, g2 = _wave(L, fine, (1, 1, -2), np.cos)
+    s0, _ = _wave(L, fine, (1, 1, -2), np.sin)
+    c1, _ = _wave(L, coarse, (1, 1, -2), np.cos)
+    assert g2 < E[1]
+    z = [np.zeros(fine), np.zeros(coarse)]
+    v, e = op.hxc_potential(L, [fine, coarse], E, z, vxc=c0)
+    np.testing.assert_allclose(v[0], c0, atol=1e-12)
+    np.testing.assert_allclose(v[1], c1, atol=1e-12)
+    assert e == 0.0
+    gy = 2 * math.pi * 1 / L[1]
+    v, _ = op.hxc_potential(L, [fine, coarse], E, z, vxc_grad=[np.zeros(fine), s0, np.zeros(fine)])
+    np.testing.assert_allclose(v[0], -gy * c0, atol=1e-11)
+    np.testing.assert_allclose(v[1], -gy * c1, atol=1e-11)
+
+
+def test_xc_terms_are_adjoint_to_the_fine_density():
+    """The level potentials of vxc and of the GGA vector potential are the
+    derivatives of w_0 <vxc, rho_fine> and w_0 sum_d <vxc_grad_d, d_d rho_fine>
+    with respect to the level densities: sum_l w_l <v_l, rho_l> equals those
+    fine-grid sums for random data (the transfer and its transpose)."""
+    L = (9.0, 10.0, 11.0)
+    meshes = [(20, 22, 24), (12, 12, 15), (6, 8, 8)]
+    E = (45.0, 15.0, 4.0)
+    rng = np.random.default_rng(12)
+    rho = [rng.standard_normal(m) for m in meshes]
+    vxc = rng.standard_normal(meshes[0])
+    vg = [rng.standard_normal(meshes[0]) for _ in range(3)]
+    vol = 990.0
+    w = [vol / float(np.prod(m)) for m in meshes]
+    rf, grad = op.fine_density(L, meshes, E, rho)
+    zero = [np.zeros(m) for m in meshes]
+    v1, _ = op.hxc_potential(L, meshes, E, zero, vxc=vxc)
+    lhs = sum(wl * float(np.vdot(a, r)) for wl, a, r in zip(w, v1, rho))
+    assert abs(lhs - w[0] * float(np.vdot(vxc, rf))) < 1e-10 * abs(lhs)
+    v2, _ = op.hxc_potential(L, meshes, E, zero, vxc_grad=vg)
+    lhs = sum(wl * float(np.vdot(a, r)) for wl, a, r in zip(w, v2, rho))
+    rhs = w[0] * sum(float(np.vdot(vg[d], grad[d])) for d in range(3))
+    assert abs(lhs - rhs) < 1e-10 * abs(rhs)
+    # the Hartree part is unchanged by the xc inputs
+    v3, e3 = op.hxc_potential(L, meshes, E, rho, vxc=vxc, vxc_grad=vg)
+    v4, e4 = op.poisson(L, meshes, E, rho)
+    assert e3 == pytest.approx(e4, rel=1e-14)
+    for a, b, c, d in zip(v3, v4, v1, v2):
+        np.testing.assert_allclose(a, b + c + d, atol=1e-10 * float(np.abs(a).max()))
