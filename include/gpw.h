@@ -152,6 +152,8 @@ typedef struct {
        degree L + 2 and L + 3.  The per-pair-image formation of matrix elements and gradient
        components from the moments is not counted. */
     double flops_grad_exec, flops_tau_exec, flops_mat_tau_exec, flops_grad_tau_exec;
+    long long poisson_scratch_bytes;          /* device scratch of gpw_poisson's spectra; the FFT library's
+                                                 work area (known once its plans exist) comes on top */
 } gpw_plan_info;
 
 /* Build a plan: screen primitive pair images, assign levels, compute their
@@ -215,6 +217,53 @@ gpw_status gpw_eval_mat_tau(gpw_plan_t plan, const double *const *vtau, double *
  * gpw_eval_grad (grad overwritten).  Enqueued on stream. */
 gpw_status gpw_eval_grad_tau(gpw_plan_t plan, const double *D, const double *const *vtau, double *grad,
                              void *stream);
+
+/* Multigrid Fourier transfer and Poisson solve (Sec. II: the Hartree
+ * potential of Eqs. (vH), (vHG) and the multigrid Fourier interpolation
+ * between the levels), the step between gpw_eval_rho and gpw_eval_mat of a
+ * Fock build.  With w_l = Omega / N_l, plane waves G = 2 pi m / L, and
+ * mask_l(G) = {|m_d| < N_{l,d} / 2 on every axis and |G|^2 < E_l (Ry, bohr^-2)}
+ * (every non-Nyquist plane wave for a single-level plan built from a mesh):
+ *   rho~(G) = sum_l mask_l(G) w_l sum_r rho_l(r) exp(-i G.r)
+ *   v_l(r)  = (1 / Omega) sum_G mask_l(G) 4 pi rho~(G) / |G|^2 exp(i G.r), G != 0
+ *   E_J     = (1 / (2 Omega)) sum_{G != 0} 4 pi |rho~(G)|^2 / |G|^2
+ * so that E_J = 1/2 sum_l w_l <v_l, rho_l> and dE_J / d rho_l = w_l v_l: v is the
+ * potential gpw_eval_mat and gpw_eval_grad take for the Hartree term.
+ * rho: host array of nlevels device pointers (level densities, read only);
+ * v: host array of nlevels device pointers, overwritten; e_j: device pointer to
+ * one double receiving E_J, or NULL.  Level 0 must hold the finest mesh; a
+ * multigrid plan must have been built from cutoffs.  FP64 throughout (hipFFT
+ * D2Z / Z2D), whatever the plan's precision.  The first call on a plan builds
+ * the FFT plans (host work, synchronous); every call takes its spectra and the
+ * FFT work area from the stream-ordered pool.  Enqueued on stream. */
+gpw_status gpw_poisson(gpw_plan_t plan, const double *const *rho, double *const *v, double *e_j, void *stream);
+
+/* The same transfer with an exchange-correlation potential given on the
+ * finest mesh (level 0), for LDA and GGA functionals (Sec. II, Eqs. (vH),
+ * (vHG), the GGA integration by parts and the divergence in Fourier space):
+ *   v~(G) = 4 pi rho~(G) / |G|^2 + w_0 F(vxc)(G) - i G . w_0 F(vxc_grad)(G)
+ * with F the discrete transform on level 0 and w_0 = Omega / N_0, restricted to
+ * level 0's plane waves, then v_l(r) = (1 / Omega) sum_G mask_l(G) v~(G)
+ * exp(i G.r) as in gpw_poisson.  vxc: device, N_0 doubles (dE_xc / d rho on the
+ * finest mesh), or NULL; vxc_grad: host array of three device pointers (the
+ * x, y, z components of dE_xc / d grad rho on the finest mesh), or NULL.
+ * E_J (e_j, device, or NULL) is the Hartree energy alone.  With rho from
+ * gpw_fine_density, sum_l w_l <v_l, rho_l> of the xc part equals
+ * w_0 (<vxc, rho> + sum_d <vxc_grad_d, d_d rho>) on the finest mesh.  Other
+ * arguments and conditions as gpw_poisson.  Enqueued on stream. */
+gpw_status gpw_hxc_potential(gpw_plan_t plan, const double *const *rho, const double *vxc,
+                             const double *const *vxc_grad, double *const *v, double *e_j, void *stream);
+
+/* The total density and its gradient on the finest mesh (level 0) by Fourier
+ * interpolation of the level densities (Sec. II: rho~ as in gpw_poisson; the
+ * GGA density gradient as the inverse transform of i G rho~):
+ *   rho(r) = (1 / Omega) sum_G rho~(G) exp(i G.r),
+ *   d_d rho(r) = (1 / Omega) sum_G i G_d rho~(G) exp(i G.r).
+ * rho: host array of nlevels device pointers; rho_fine: device, N_0 doubles,
+ * or NULL; grad: host array of three device pointers (N_0 doubles each), or
+ * NULL.  Conditions as gpw_poisson.  Enqueued on stream. */
+gpw_status gpw_fine_density(gpw_plan_t plan, const double *const *rho, double *rho_fine, double *const *grad,
+                            void *stream);
 
 /* One task of a batched launch. */
 typedef enum {

@@ -92,6 +92,7 @@ class gpw_plan_info(C.Structure):
         ("flops_tau_exec", C.c_double),
         ("flops_mat_tau_exec", C.c_double),
         ("flops_grad_tau_exec", C.c_double),
+        ("poisson_scratch_bytes", C.c_longlong),
     ]
 
 
@@ -108,7 +109,8 @@ class gpw_task(C.Structure):
 
 EXPORTS = ("gpw_plan", "gpw_plan_destroy", "gpw_plan_query", "gpw_eval_rho", "gpw_eval_mat",
            "gpw_eval_grad", "gpw_eval_tau", "gpw_eval_mat_tau", "gpw_eval_grad_tau", "gpw_eval_batch",
-           "gpw_eval_mat_noalloc", "gpw_last_error")
+           "gpw_eval_mat_noalloc", "gpw_poisson", "gpw_hxc_potential", "gpw_fine_density",
+           "gpw_last_error")
 GPW_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 _lib = None
@@ -140,6 +142,9 @@ def load(path: str = LIB_PATH):
     lib.gpw_eval_grad_tau.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gpw_eval_batch.argtypes = [C.POINTER(gpw_task), C.c_int, C.c_void_p]
     lib.gpw_eval_mat_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_poisson.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gpw_hxc_potential.argtypes = [C.c_void_p] * 7
+    lib.gpw_fine_density.argtypes = [C.c_void_p] * 5
     lib.gpw_last_error.restype = C.c_char_p
     for name in EXPORTS:
         if name != "gpw_last_error":
@@ -279,6 +284,7 @@ class PlanHandle:
             "scratch_bytes": list(info.scratch_bytes),
             "flops_grad_exec": info.flops_grad_exec, "flops_tau_exec": info.flops_tau_exec,
             "flops_mat_tau_exec": info.flops_mat_tau_exec, "flops_grad_tau_exec": info.flops_grad_tau_exec,
+            "poisson_scratch_bytes": info.poisson_scratch_bytes,
         }
 
     def close(self):
@@ -329,6 +335,46 @@ def gpw_eval_grad_tau(plan: PlanHandle, D, vtau, grad, stream=None):
     arr = _level_ptrs(plan, vtau, "vtau")
     _check(load().gpw_eval_grad_tau(plan.handle, _mat_ptr(plan, D, "D"), arr, _grad_ptr(plan, grad, "grad"),
                                     _stream_handle(stream)))
+
+
+def gpw_poisson(plan: PlanHandle, rho, v, e_j=None, stream=None):
+    """rho, v: one float64 device grid per level; e_j: a one-element float64
+    device tensor receiving E_J, or None."""
+    ra = _level_ptrs(plan, rho, "rho")
+    va = _level_ptrs(plan, v, "v")
+    ep = None if e_j is None else _dev_ptr(e_j, "e_j", 1, plan.device)
+    _check(load().gpw_poisson(plan.handle, ra, va, ep, _stream_handle(stream)))
+
+
+def _fine_ptr(plan, t, what):
+    return _dev_ptr(t, what, plan.n_grid[0], plan.device)
+
+
+def gpw_hxc_potential(plan: PlanHandle, rho, v, vxc=None, vxc_grad=None, e_j=None, stream=None):
+    """Level potentials of the Hartree term plus a fine-grid XC potential
+    (vxc: one level-0 grid) and GGA vector potential (vxc_grad: three level-0
+    grids), either may be None."""
+    ra = _level_ptrs(plan, rho, "rho")
+    va = _level_ptrs(plan, v, "v")
+    xp = None if vxc is None else _fine_ptr(plan, vxc, "vxc")
+    ga = None
+    if vxc_grad is not None:
+        if len(vxc_grad) != 3:
+            raise ValueError("vxc_grad: expected three components")
+        ga = _ptr_array([_fine_ptr(plan, t, f"vxc_grad[{d}]") for d, t in enumerate(vxc_grad)])
+    ep = None if e_j is None else _dev_ptr(e_j, "e_j", 1, plan.device)
+    _check(load().gpw_hxc_potential(plan.handle, ra, xp, ga, va, ep, _stream_handle(stream)))
+
+
+def gpw_fine_density(plan: PlanHandle, rho, rho_fine=None, grad=None, stream=None):
+    ra = _level_ptrs(plan, rho, "rho")
+    rp = None if rho_fine is None else _fine_ptr(plan, rho_fine, "rho_fine")
+    ga = None
+    if grad is not None:
+        if len(grad) != 3:
+            raise ValueError("grad: expected three components")
+        ga = _ptr_array([_fine_ptr(plan, t, f"grad[{d}]") for d, t in enumerate(grad)])
+    _check(load().gpw_fine_density(plan.handle, ra, rp, ga, _stream_handle(stream)))
 
 
 def gpw_eval_mat_noalloc(plan: PlanHandle, v, M, stream=None):

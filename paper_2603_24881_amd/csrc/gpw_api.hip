@@ -56,6 +56,7 @@ struct DeviceGuard {
 void free_plan(gpw_plan_s *pl)
 {
     if (!pl) return;
+    gpw::poisson_free(pl);
     for (void *p : pl->allocations)
         if (p) (void)hipFree(p);
     delete pl;
@@ -273,6 +274,7 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
                      (long long)n_ps * (3 * sizeof(int) + 2 * sizeof(double)) + 24LL * pl->natm;
     for (int op = GPW_OP_RHO; op <= GPW_OP_GRAD_TAU; ++op)
         I.scratch_bytes[op] = (long long)gpw::eval_scratch_bytes(pl, op);
+    I.poisson_scratch_bytes = (long long)gpw::poisson_spectra_bytes(pl);
     *out = pl;
     return GPW_OK;
 }
@@ -379,6 +381,64 @@ gpw_status gpw_eval_grad_tau(gpw_plan_t plan, const double *D, const double *con
 {
     gpw_task t{plan, GPW_OP_GRAD_TAU, D, vtau, nullptr, grad};
     return run_tasks(&t, 1, stream, "gpw_eval_grad_tau");
+}
+
+// Preconditions of the Fourier-space calls: level 0 holds the finest mesh on
+// every axis, and a multigrid plan has its level cutoffs (the masks).
+static gpw_status check_fourier(const gpw_plan_s *pl, const void *const *rho, const char *what)
+{
+    if (!pl) return fail(GPW_EINVAL, std::string(what) + ": NULL plan");
+    gpw_status s = check_levels(pl, rho, what);
+    if (s != GPW_OK) return s;
+    for (int l = 1; l < pl->nlevels; ++l)
+        for (int d = 0; d < 3; ++d)
+            if (pl->geom[l].N[d] > pl->geom[0].N[d])
+                return fail(GPW_EINVAL, std::string(what) + ": level 0 must hold the finest mesh on every axis");
+    if (pl->nlevels > 1)
+        for (int l = 0; l < pl->nlevels; ++l)
+            if (!(pl->cut_ry[l] > 0.0))
+                return fail(GPW_EINVAL, std::string(what) + ": a multigrid plan needs the level cutoffs");
+    return GPW_OK;
+}
+
+gpw_status gpw_hxc_potential(gpw_plan_t plan, const double *const *rho, const double *vxc,
+                             const double *const *vxc_grad, double *const *v, double *e_j, void *stream)
+{
+    gpw_status s = check_fourier(plan, (const void *const *)rho, "gpw_hxc_potential");
+    if (s != GPW_OK) return s;
+    s = check_levels(plan, (const void *const *)v, "gpw_hxc_potential");
+    if (s != GPW_OK) return s;
+    if (vxc_grad && (!vxc_grad[0] || !vxc_grad[1] || !vxc_grad[2]))
+        return fail(GPW_EINVAL, "gpw_hxc_potential: NULL component of vxc_grad");
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_hxc_potential");
+    const hipError_t e = gpw::poisson_run(plan, rho, vxc, vxc_grad, v, e_j, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_hxc_potential");
+}
+
+gpw_status gpw_poisson(gpw_plan_t plan, const double *const *rho, double *const *v, double *e_j, void *stream)
+{
+    gpw_status s = check_fourier(plan, (const void *const *)rho, "gpw_poisson");
+    if (s != GPW_OK) return s;
+    s = check_levels(plan, (const void *const *)v, "gpw_poisson");
+    if (s != GPW_OK) return s;
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_poisson");
+    const hipError_t e = gpw::poisson_run(plan, rho, nullptr, nullptr, v, e_j, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_poisson");
+}
+
+gpw_status gpw_fine_density(gpw_plan_t plan, const double *const *rho, double *rho_fine, double *const *grad,
+                            void *stream)
+{
+    gpw_status s = check_fourier(plan, (const void *const *)rho, "gpw_fine_density");
+    if (s != GPW_OK) return s;
+    if (grad && (!grad[0] || !grad[1] || !grad[2]))
+        return fail(GPW_EINVAL, "gpw_fine_density: NULL component of grad");
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "gpw_fine_density");
+    const hipError_t e = gpw::fine_density_run(plan, rho, rho_fine, grad, (hipStream_t)stream);
+    return e == hipSuccess ? GPW_OK : hip_fail(e, "gpw_fine_density");
 }
 
 gpw_status gpw_eval_mat_noalloc(gpw_plan_t plan, const double *const *v, double *M, void *stream)

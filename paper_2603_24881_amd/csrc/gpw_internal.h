@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -262,6 +263,8 @@ struct PartitionInput {
     PlanConst pc;
 };
 
+struct PoissonState;   // FFT plans of the multigrid transfer (gpw_poisson.hip)
+
 }  // namespace gpw
 
 struct gpw_plan_s {
@@ -298,6 +301,10 @@ struct gpw_plan_s {
     gpw_plan_info info{};
     int max_axis_blocks = 0;   // longest per-axis block list of a pair image
     std::vector<void *> allocations;
+
+    // multigrid transfer + Poisson: FFT plans, created on first use
+    gpw::PoissonState *poisson = nullptr;
+    std::mutex poisson_mu;
 };
 
 namespace gpw {
@@ -320,6 +327,16 @@ hipError_t eval_noalloc(const TaskRef &t, hipStream_t st);
 hipError_t noalloc_scratch(int dev, unsigned char **ptr);
 // Device scratch one evaluation of op (gpw_op) takes from the stream-ordered pool.
 size_t eval_scratch_bytes(const gpw_plan_s *pl, int op);
+// Multigrid transfer + Poisson solve (gpw_poisson.hip): enqueue on st; free
+// the FFT plans; device bytes of the spectra one call takes from the pool
+// (the FFT library's work area comes on top).
+hipError_t poisson_run(gpw_plan_s *pl, const double *const *rho, const double *vxc, const double *const *vxc_grad,
+                       double *const *v, double *ej, hipStream_t st);
+// density (and optionally its gradient) on the finest mesh from the level densities
+hipError_t fine_density_run(gpw_plan_s *pl, const double *const *rho, double *rho_fine, double *const *grad,
+                            hipStream_t st);
+void poisson_free(gpw_plan_s *pl);
+size_t poisson_spectra_bytes(const gpw_plan_s *pl);
 // LDS bytes a workgroup of the pair-major kernels (mat, grad) needs for a plan
 // whose longest per-axis block list of a pair image has emax entries.
 size_t pair_kernel_lds_bytes(int emax, int precision);

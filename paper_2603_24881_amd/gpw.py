@@ -77,9 +77,9 @@ class GPW:
         return out
 
     def poisson(self):
-        """Multigrid transfer + Poisson solver for this plan's levels, on its device."""
-        from .poisson import MultigridPoisson
-        return MultigridPoisson(self.cell, self.meshes, self.cutoffs_ry, device=self._dev())
+        """Multigrid transfer + Poisson step of this plan (gpw_poisson)."""
+        from .poisson import Poisson
+        return Poisson(self)
 
     def close(self):
         self.plan.close()

@@ -1,117 +1,97 @@
-"""Multigrid transfer and Poisson solve between eval_rho and eval_mat.
+"""Multigrid transfer and Poisson solve between eval_rho and eval_mat, through
+the library's gpw_poisson (hipFFT and HIP kernels on the plan's device).
 
-This is the reciprocal-space step that sits between the two kernels of the
-Fock build (Sec. II, the multigrid Fourier interpolation and the Hartree
-potential): the level densities are brought to one set of plane-wave
-coefficients, the Poisson equation is solved there, and the potential is
-handed back to every level.  It runs with ``torch.fft`` on whatever device
-the grids live on and is not part of the timed hot path.
+For level l with mesh N_l (weight w_l = Omega / N_l), plane waves G = 2 pi m / L
+and mask_l(G) = {|m_d| < N_d / 2, |G|^2 < E_l}:
 
-For level l with mesh N_l, points r_j = j h (h = L / N_l), the plane waves
-G = 2 pi m / L (integer m, |m_d| < N_d / 2) and the mask |G|^2 < E_l (E_l the
-level cutoff in Ry, |G|^2 in bohr^-2; a strict sphere, the same for both
-directions so that the transfer is self-adjoint):
+  rho~(G)  = sum_l mask_l(G) w_l FFT(rho_l)(G)
+  v_l(r)   = (1 / Omega) sum_G mask_l(G) 4 pi rho~(G) / |G|^2 exp(i G.r)   (G != 0)
+  E_J      = (1 / (2 Omega)) sum_{G != 0} 4 pi |rho~(G)|^2 / |G|^2
 
-  rho~(G) = sum_l mask_l(G) (Omega / N_l) sum_j rho_l(r_j) exp(-i G r_j)
-  v~(G)   = 4 pi rho~(G) / |G|^2   (G != 0; v~(0) = 0, neutralising background)
-  v_l(r_j) = (1 / Omega) sum_G mask_l(G) v~(G) exp(i G r_j)
-  E_J     = (1 / (2 Omega)) sum_{G != 0} 4 pi |rho~(G)|^2 / |G|^2
-
-so that E_J = 1/2 sum_l w_l <v_l, rho_l> with w_l = Omega / N_l, and
-dE_J / d rho_l(r_j) = w_l v_l(r_j).  A level without a cutoff (a mesh given
-directly) keeps every non-Nyquist plane wave of its mesh.
+(Sec. II: the Hartree potential and the multigrid Fourier interpolation), so
+E_J = 1/2 sum_l w_l <v_l, rho_l> and dE_J / d rho_l = w_l v_l.
 """
 from __future__ import annotations
 
-import math
-
-import numpy as np
+from . import _lib
 
 
-class MultigridPoisson:
-    """Transfer + Poisson for one cell and one set of level meshes.
+class Poisson:
+    """The transfer + Poisson step of one plan (``GPW.poisson()``)."""
 
-    cell: (3,) orthorhombic side lengths (bohr); meshes: per level (N0, N1, N2),
-    finest first; cutoffs_ry: per level cutoff (Ry) or None for "all plane
-    waves of the mesh"."""
-
-    def __init__(self, cell, meshes, cutoffs_ry=None, device="cpu"):
-        import torch
-        self.L = np.asarray(cell, dtype=np.float64).reshape(3)
-        self.meshes = [tuple(int(x) for x in m) for m in meshes]
-        self.nlevels = len(self.meshes)
-        if cutoffs_ry is not None and len(cutoffs_ry) == 0:
-            cutoffs_ry = None
-        if cutoffs_ry is None and self.nlevels > 1:
-            raise ValueError("several levels need their cutoffs")
-        self.cutoffs = None if cutoffs_ry is None else [float(e) for e in cutoffs_ry]
-        self.volume = float(np.prod(self.L))
-        self.device = torch.device(device)
-        fine = self.meshes[0]
-        for m in self.meshes[1:]:
-            if any(a > b for a, b in zip(m, fine)):
-                raise ValueError("level 0 must hold the finest mesh")
-        self.fine = fine
-        # |G|^2 on the fine coefficient grid
-        g2 = np.zeros(fine)
-        for d in range(3):
-            m = np.fft.fftfreq(fine[d]) * fine[d]
-            g = 2.0 * math.pi * m / self.L[d]
-            shape = [1, 1, 1]
-            shape[d] = fine[d]
-            g2 = g2 + (g ** 2).reshape(shape)
-        self.g2 = torch.as_tensor(g2, device=self.device)
-        coul = np.zeros(fine)
-        nz = g2 > 0
-        coul[nz] = 4.0 * math.pi / g2[nz]
-        self.coulomb = torch.as_tensor(coul, device=self.device)
-        # per level: flat indices of its masked plane waves in its own grid and in the fine grid
-        self.src, self.dst = [], []
-        for l, mesh in enumerate(self.meshes):
-            ms = [np.fft.fftfreq(n) * n for n in mesh]
-            mx, my, mz = np.meshgrid(*ms, indexing="ij")
-            ok = np.ones(mesh, dtype=bool)
-            for d, md in enumerate((mx, my, mz)):
-                ok &= np.abs(md) < mesh[d] / 2.0          # no Nyquist plane
-            if self.cutoffs is not None:
-                gg = sum((2.0 * math.pi * md / self.L[d]) ** 2 for d, md in enumerate((mx, my, mz)))
-                ok &= gg < self.cutoffs[l]
-            src = np.flatnonzero(ok.ravel())
-            fx = np.mod(mx.ravel()[src], fine[0]).astype(np.int64)
-            fy = np.mod(my.ravel()[src], fine[1]).astype(np.int64)
-            fz = np.mod(mz.ravel()[src], fine[2]).astype(np.int64)
-            dst = (fx * fine[1] + fy) * fine[2] + fz
-            self.src.append(torch.as_tensor(src, device=self.device))
-            self.dst.append(torch.as_tensor(dst, device=self.device))
+    def __init__(self, gpw):
+        self.g = gpw
 
     def weights(self):
-        return [self.volume / float(np.prod(m)) for m in self.meshes]
+        return list(self.g.weights)
 
-    def coefficients(self, rho):
-        """rho~ on the fine coefficient grid from the level densities."""
-        import torch
-        acc = torch.zeros(self.fine, dtype=torch.complex128, device=self.device).reshape(-1)
-        for l, r in enumerate(rho):
-            f = torch.fft.fftn(r.to(torch.float64)).reshape(-1) * (self.volume / float(np.prod(self.meshes[l])))
-            acc = acc.index_add(0, self.dst[l], f[self.src[l]])
-        return acc.reshape(self.fine)
+    def solve(self, rho, out=None, stream=None):
+        """(v_l per level, E_J as a float); synchronises the stream for E_J."""
+        v, ej = self.solve_async(rho, out=out, stream=stream)
+        return v, float(ej.item())
 
-    def solve(self, rho):
-        """(v_l per level, E_J) from the level densities."""
+    def solve_async(self, rho, out=None, stream=None):
+        """(v_l per level, E_J as a one-element device tensor), enqueued only."""
         import torch
-        rt = self.coefficients(rho)
-        vt = (rt * self.coulomb).reshape(-1)
-        e_j = float((rt.abs() ** 2 * self.coulomb).sum().item()) / (2.0 * self.volume)
-        out = []
-        for l, mesh in enumerate(self.meshes):
-            buf = torch.zeros(int(np.prod(mesh)), dtype=torch.complex128, device=self.device)
-            buf[self.src[l]] = vt[self.dst[l]]
-            n = float(np.prod(mesh))
-            v = torch.fft.ifftn(buf.reshape(mesh)).real * (n / self.volume)
-            out.append(v.contiguous())
-        return out, e_j
+        v = self.g.new_grids() if out is None else out
+        ej = torch.empty(1, dtype=torch.float64, device=v[0].device)
+        _lib.gpw_poisson(self.g.plan, [r.contiguous() for r in rho], v, ej, stream)
+        return v, ej
+
+    def hxc(self, rho, vxc=None, vxc_grad=None, out=None, stream=None):
+        """(v_l per level, E_J device scalar) of the Hartree term plus a
+        fine-grid XC potential vxc and GGA vector potential vxc_grad (three
+        fine grids); either may be None."""
+        import torch
+        v = self.g.new_grids() if out is None else out
+        ej = torch.empty(1, dtype=torch.float64, device=v[0].device)
+        _lib.gpw_hxc_potential(self.g.plan, [r.contiguous() for r in rho], v, vxc=vxc, vxc_grad=vxc_grad, e_j=ej,
+                               stream=stream)
+        return v, ej
+
+    def fine_density(self, rho, gradient=True, stream=None):
+        """(rho, [d_x rho, d_y rho, d_z rho] or None) on the finest mesh."""
+        import torch
+        shape = tuple(self.g.meshes[0])
+        dev = rho[0].device
+        rf = torch.empty(shape, dtype=torch.float64, device=dev)
+        grad = [torch.empty(shape, dtype=torch.float64, device=dev) for _ in range(3)] if gradient else None
+        _lib.gpw_fine_density(self.g.plan, [r.contiguous() for r in rho], rho_fine=rf, grad=grad, stream=stream)
+        return rf, grad
 
     def energy(self, rho):
-        """E_J as a differentiable torch scalar (gradient w_l v_l per level)."""
-        rt = self.coefficients(rho)
-        return (rt.abs() ** 2 * self.coulomb).sum() / (2.0 * self.volume)
+        """E_J as a differentiable torch scalar: its gradient with respect to
+        rho_l is w_l v_l."""
+        return _HartreeEnergy.apply(self, *rho)
+
+
+def _hartree_fn():
+    import torch
+
+    class HartreeEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, p, *rho):
+            v, ej = p.solve_async([r.detach() for r in rho])
+            ctx.save_for_backward(*v)
+            ctx.w = p.weights()
+            return ej[0]
+
+        @staticmethod
+        def backward(ctx, g):
+            v = ctx.saved_tensors
+            return (None, *[g * w * vl for w, vl in zip(ctx.w, v)])
+
+    return HartreeEnergy
+
+
+class _Lazy:
+    fn = None
+
+    @classmethod
+    def apply(cls, *args):
+        if cls.fn is None:
+            cls.fn = _hartree_fn()
+        return cls.fn.apply(*args)
+
+
+_HartreeEnergy = _Lazy

@@ -207,10 +207,10 @@ def summarize(requests):
 # ---------------------------------------------------------------- GPU side
 
 class GPUExecutor:
-    """Runs requests on one device through the C ABI.  Plans and their
-    Poisson tables are built at ``register`` (their size is then known, and
-    the FFT plans of their meshes are warmed up) and stay resident until the
-    scheduler unloads them."""
+    """Runs requests on one device through the C ABI.  Plans are built at
+    ``register`` (their size is then known, and the FFT plans of their Poisson
+    step are built and warmed up) and stay resident until the scheduler
+    unloads them."""
 
     def __init__(self, device=0, precision="fp64", keep_results=False):
         import torch
@@ -220,7 +220,7 @@ class GPUExecutor:
         self.precision = precision
         self.keep = keep_results
         self.systems = {}
-        self.plans = {}         # key -> (GPW, MultigridPoisson)
+        self.plans = {}         # key -> (GPW, its Poisson step)
         self.sizes = {}         # key -> plan bytes
         self.req_sizes = {}     # key -> {kind: bytes}
         self.n_occ = {}
@@ -234,20 +234,20 @@ class GPUExecutor:
         # which can take seconds: do it here, not in a request's latency
         p.solve([self.torch.zeros(tuple(m), dtype=self.torch.float64, device=self.dev) for m in g.meshes])
         info = g.info
-        fine = int(np.prod(info["mesh"][0]))
         ngrid = sum(int(np.prod(m)) for m in info["mesh"])
-        poisson_bytes = 16 * fine * 3 + 16 * sum(int(t.numel()) for t in p.src + p.dst)
-        self.sizes[key] = int(info["device_bytes"]) + poisson_bytes
+        # gpw_poisson's spectra; its FFT work area is bounded by the same size
+        poisson_bytes = 2 * int(info["poisson_scratch_bytes"])
+        self.sizes[key] = int(info["device_bytes"])
         n2 = 8 * info["n_ao"] ** 2
         grids = 8 * ngrid
         # the library's own scratch of each operation (packed D of the collocation;
         # block-ordered potentials, with their periodic column extension, of the
         # integration and the gradient; the symmetrised D of the gradient)
         scr_rho, scr_mat, scr_grad = (int(x) for x in info["scratch_bytes"][:3])
-        # D, the level densities and then potentials, the Poisson step's FFT
-        # temporaries; the collocation's and the second stage's scratch never
-        # coexist within one request
-        common = n2 + 2 * grids + 16 * fine * 3
+        # D, the level densities and then potentials, the Poisson step's
+        # spectra and FFT work area; the collocation's and the second stage's
+        # scratch never coexist within one request
+        common = n2 + 2 * grids + poisson_bytes
         self.req_sizes[key] = {FOCK: common + n2 + max(scr_rho, scr_mat),
                                GRAD: common + 24 * info["natm"] + max(scr_rho, scr_grad)}
         self.n_occ[key] = system.n_occ
@@ -289,9 +289,9 @@ class GPUExecutor:
 
     def _finish_poisson(self, r):
         _, p = self.plans[r.system]
-        v, e = p.solve(r.state["rho"])
+        v, e = p.solve_async(r.state["rho"])
         r.state["v"] = v
-        r.state["E_J"] = e
+        r.state["E_J"] = e          # device scalar, read when the request ends
         del r.state["rho"]
 
     def _output(self, r):
@@ -354,7 +354,7 @@ class GPUExecutor:
 
     def end(self, r):
         key = "J" if r.kind == FOCK else "grad"
-        r.result = {"E_J": r.state["E_J"]}
+        r.result = {"E_J": float(r.state["E_J"].item())}
         if self.keep:
             r.result[key] = r.state["out"]
         r.state = {}

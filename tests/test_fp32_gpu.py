@@ -1,8 +1,9 @@
 """FP32 variant on the diamond configuration (216 C, 5 levels): errors of
 E_J, the Coulomb matrix J = V_{mu nu}(v_H) and the gradient dE_J/dR against
 the FP64 oracle, next to those of the FP64 kernels.  The Hartree potential
-of each side comes from the multigrid Poisson harness applied to that side's
-density."""
+of each side comes from the multigrid Poisson step applied to that side's
+density (the library's gpw_poisson for the GPU, the Poisson oracle for the
+oracle)."""
 from __future__ import annotations
 
 import numpy as np
@@ -11,7 +12,6 @@ import pytest
 import oracle
 from gpu_helpers import log, rel_err, to_dev, to_np
 from paper_2603_24881_amd import synth
-from paper_2603_24881_amd.poisson import MultigridPoisson
 
 pytestmark = pytest.mark.gpu
 
@@ -31,14 +31,11 @@ def _gpu_pipeline(s, D, precision):
 
 
 def test_fp32_errors_on_diamond():
-    import torch
+    from oracle import poisson as opoisson
     s = synth.config4()
     D = synth.make_density(s)
     o = oracle.Oracle(s)
-    rho = [torch.as_tensor(r) for r in o.rho(D)]
-    p = MultigridPoisson(s.cell, o.meshes, s.ke_cutoff_ry)
-    v, e_o = p.solve(rho)
-    vn = [x.numpy() for x in v]
+    vn, e_o = opoisson.poisson(s.cell, o.meshes, s.ke_cutoff_ry, o.rho(D))
     J_o, F_o = o.mat(vn), o.grad(D, vn)
     rep = {}
     for prec in ("fp64", "fp32"):
