@@ -52,6 +52,7 @@ class _OSys(C.Structure):
         ("tau", C.c_double),
         ("atom_mask", C.POINTER(C.c_ubyte)),
         ("mask_either", C.c_int),
+        ("lat", C.POINTER(C.c_double)),
     ]
 
 
@@ -101,7 +102,16 @@ class Oracle:
     def __init__(self, system, tau: float | None = None, atom_mask=None, mask_either: bool = False):
         self.s = system
         lib = _load()
-        self.cell = np.ascontiguousarray(system.cell, dtype=np.float64)
+        cell = np.asarray(system.cell, dtype=np.float64)
+        # a 3 x 3 cell holds the lattice vectors as rows; a diagonal one is orthorhombic
+        self.lat = None
+        if cell.shape == (3, 3):
+            if np.count_nonzero(cell - np.diag(np.diag(cell))) == 0:
+                cell = np.diag(cell).copy()
+            else:
+                self.lat = np.ascontiguousarray(cell)
+                cell = np.sqrt((cell ** 2).sum(axis=1))      # |a_d| for the mesh rule
+        self.cell = np.ascontiguousarray(cell, dtype=np.float64)
         self.coords = np.ascontiguousarray(system.coords, dtype=np.float64)
         self.shell_atom = np.ascontiguousarray(system.shell_atom, dtype=np.int32)
         self.shell_l = np.ascontiguousarray(system.shell_l, dtype=np.int32)
@@ -142,6 +152,7 @@ class Oracle:
         st.atom_mask = (self.atom_mask.ctypes.data_as(C.POINTER(C.c_ubyte))
                         if self.atom_mask is not None else None)
         st.mask_either = 1 if mask_either else 0
+        st.lat = _dp(self.lat) if self.lat is not None else None
         self._st = st
         self.counts = np.zeros(NCOUNT, dtype=np.int64)
 
@@ -150,8 +161,11 @@ class Oracle:
     def meshes(self):
         return [tuple(int(x) for x in m) for m in self.mesh]
 
+    def volume(self):
+        return float(abs(np.linalg.det(self.lat))) if self.lat is not None else float(np.prod(self.cell))
+
     def weights(self):
-        vol = float(np.prod(self.cell))
+        vol = self.volume()
         return [vol / float(np.prod(m)) for m in self.mesh]
 
     def _concat(self, grids):

@@ -8,7 +8,8 @@
  * path: its own pair enumeration, truncation, level rule, mesh rule, grid
  * evaluation and AO ordering are written here from the paper's definitions.
  *
- * What it computes (all FP64, Gamma point, orthorhombic cell):
+ * What it computes (all FP64, Gamma point; orthorhombic cells with a 1-D table
+ * per axis, general cells point by point, see eval_pair_general):
  *
  *   rho_l[j mod N] = sum over ordered primitive-shell pairs (a,k),(b,l) and
  *                    lattice vectors T of the second one, with level(p) = l,
@@ -90,7 +91,33 @@ typedef struct {
     double tau;
     const unsigned char *atom_mask;  /* optional: only pairs whose first atom is set */
     int mask_either;                 /* with atom_mask: pairs with either atom set */
+    const double *lat;               /* optional general cell: lattice vectors a_d as rows (9
+                                        doubles); NULL: the orthorhombic cell[] */
 } osys;
+
+/* Inverse of the lattice matrix (rows a_d): r = u . A, u = r . inv; returns det. */
+static double lat_inverse(const double *a, double *inv)
+{
+    double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                 a[2] * (a[3] * a[7] - a[4] * a[6]);
+    inv[0] = (a[4] * a[8] - a[5] * a[7]) / det;
+    inv[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+    inv[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+    inv[3] = (a[5] * a[6] - a[3] * a[8]) / det;
+    inv[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+    inv[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+    inv[6] = (a[3] * a[7] - a[4] * a[6]) / det;
+    inv[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+    inv[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+    return det;
+}
+
+/* Length of column d of inv: the change of fractional coordinate u_d per unit
+ * distance along its steepest direction. */
+static double inv_col_norm(const double *inv, int d)
+{
+    return sqrt(inv[d] * inv[d] + inv[3 + d] * inv[3 + d] + inv[6 + d] * inv[6 + d]);
+}
 
 /* ---------------------------------------------------------------- basics */
 
@@ -219,10 +246,20 @@ static void for_each_pair(const osys *s, pair_fn fn, void *ctx)
         double dmax = sqrt(Q / mu);
         const double *A = s->coords + 3 * atom_a, *B = s->coords + 3 * atom_b;
         long nlo[3], nhi[3];
+        double inv[9];
+        if (s->lat) lat_inverse(s->lat, inv);
         for (int d = 0; d < 3; ++d) {
-            double ab = A[d] - B[d];
-            nlo[d] = (long)ceil((ab - dmax) / s->cell[d]) - 1;
-            nhi[d] = (long)floor((ab + dmax) / s->cell[d]) + 1;
+            if (s->lat) {
+                /* |A - B - T| <= dmax bounds the fractional coordinate of A - B - T */
+                double u = (A[0] - B[0]) * inv[d] + (A[1] - B[1]) * inv[3 + d] + (A[2] - B[2]) * inv[6 + d];
+                double du = dmax * inv_col_norm(inv, d);
+                nlo[d] = (long)ceil(u - du) - 1;
+                nhi[d] = (long)floor(u + du) + 1;
+            } else {
+                double ab = A[d] - B[d];
+                nlo[d] = (long)ceil((ab - dmax) / s->cell[d]) - 1;
+                nhi[d] = (long)floor((ab + dmax) / s->cell[d]) + 1;
+            }
         }
         for (long n0 = nlo[0]; n0 <= nhi[0]; ++n0)
             for (long n1 = nlo[1]; n1 <= nhi[1]; ++n1)
@@ -231,7 +268,10 @@ static void for_each_pair(const osys *s, pair_fn fn, void *ctx)
                     double d2 = 0.0;
                     for (int d = 0; d < 3; ++d) {
                         p.A[d] = A[d];
-                        p.B[d] = B[d] + nn[d] * s->cell[d];
+                        if (s->lat)   /* T = n_0 a_0 + n_1 a_1 + n_2 a_2 */
+                            p.B[d] = B[d] + nn[0] * s->lat[d] + nn[1] * s->lat[3 + d] + nn[2] * s->lat[6 + d];
+                        else
+                            p.B[d] = B[d] + nn[d] * s->cell[d];
                         double t = p.A[d] - p.B[d];
                         d2 += t * t;
                     }
@@ -324,9 +364,223 @@ typedef struct {
     long *counts;              /* nthreads * OR_NCNT */
 } octx;
 
+/* The contributions of one pair image at one grid point (wrapped flat index
+ * wflat of its level; sample slot sidx in the sampled modes), from the 1-D
+ * tables ga, gb (n[d] entries per power along axis d) at table position tt. */
+static void point_terms(const osys *s, octx *c, const opair *p, double *const *ga, double *const *gb,
+                        const long *n, const long *tt, const int (*ax)[3], const int (*bx)[3], long wflat,
+                        long sidx, double w, double *out)
+{
+    const int lv = p->level, la = p->la, lb = p->lb, na = ncart(la), nb = ncart(lb);
+    const int mu0 = c->ao_off[p->sa], nu0 = c->ao_off[p->sb];
+    const double cc = p->ca * p->cb;
+    double Ga[OR_NCART], Gb[OR_NCART];
+    for (int m = 0; m < na; ++m)
+        Ga[m] = ga[0][ax[m][0] * n[0] + tt[0]] * ga[1][ax[m][1] * n[1] + tt[1]] *
+                ga[2][ax[m][2] * n[2] + tt[2]];
+    for (int m = 0; m < nb; ++m)
+        Gb[m] = gb[0][bx[m][0] * n[0] + tt[0]] * gb[1][bx[m][1] * n[1] + tt[1]] *
+                gb[2][bx[m][2] * n[2] + tt[2]];
+    if (c->mode >= MODE_TAU) {
+        double Da[OR_NCART][3], Db[OR_NCART][3];   /* grad G along each axis */
+        for (int m = 0; m < na; ++m)
+            for (int d = 0; d < 3; ++d) Da[m][d] = cart_d1(ga, n, tt, ax[m], p->aa, d);
+        for (int m = 0; m < nb; ++m)
+            for (int d = 0; d < 3; ++d) Db[m][d] = cart_d1(gb, n, tt, bx[m], p->ab, d);
+        if (c->mode == MODE_TAU) {
+            double acc = 0.0;
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    double dot = Da[i][0] * Db[j][0] + Da[i][1] * Db[j][1] + Da[i][2] * Db[j][2];
+                    acc += c->D[(long)(mu0 + i) * c->n_ao + nu0 + j] * dot;
+                }
+            if (c->nsamp > 0) out[sidx] += 0.5 * cc * acc;
+            else out[c->lvl_off[lv] + wflat] += 0.5 * cc * acc;
+        } else if (c->mode == MODE_MAT_TAU) {
+            double f = 0.5 * w * c->V[c->lvl_off[lv] + wflat] * cc;
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    double dot = Da[i][0] * Db[j][0] + Da[i][1] * Db[j][1] + Da[i][2] * Db[j][2];
+                    long o;
+                    if (c->sp_slot) o = c->sp_slot[(long)p->sa * s->nshell + p->sb] + i * nb + j;
+                    else o = (long)(mu0 + i) * c->n_ao + nu0 + j;
+                    out[o] += f * dot;
+                }
+        } else {
+            /* d/dA_e grad G_a = -d/dr_e grad G_a (G_a depends on r - A) */
+            double f = 0.5 * w * c->V[c->lvl_off[lv] + wflat] * cc;
+            double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    double Dij = c->D[(long)(mu0 + i) * c->n_ao + nu0 + j];
+                    if (Dij == 0.0) return;
+                    for (int e = 0; e < 3; ++e)
+                        for (int d = 0; d < 3; ++d) {
+                            gA[e] -= Dij * cart_d2(ga, n, tt, ax[i], p->aa, e, d) * Db[j][d];
+                            gB[e] -= Dij * Da[i][d] * cart_d2(gb, n, tt, bx[j], p->ab, e, d);
+                        }
+                }
+            for (int e = 0; e < 3; ++e) {
+                out[3 * p->atom_a + e] += f * gA[e];
+                out[3 * p->atom_b + e] += f * gB[e];
+            }
+        }
+        return;
+    }
+    if (c->mode == MODE_RHO) {
+        double acc = 0.0;
+        for (int i = 0; i < na; ++i) {
+            double t = 0.0;
+            for (int j = 0; j < nb; ++j)
+                t += c->D[(long)(mu0 + i) * c->n_ao + nu0 + j] * Gb[j];
+            acc += Ga[i] * t;
+        }
+        if (c->nsamp > 0) out[sidx] += cc * acc;
+        else out[c->lvl_off[lv] + wflat] += cc * acc;
+    } else if (c->mode == MODE_MAT) {
+        double f = w * c->V[c->lvl_off[lv] + wflat] * cc;
+        long base;
+        long stride;
+        if (c->sp_slot) {
+            base = c->sp_slot[(long)p->sa * s->nshell + p->sb];
+            if (base < 0) return;
+            stride = nb;
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j)
+                    out[base + i * stride + j] += f * Ga[i] * Gb[j];
+        } else {
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j)
+                    out[(long)(mu0 + i) * c->n_ao + nu0 + j] += f * Ga[i] * Gb[j];
+        }
+    } else {
+        /* d/dA_d of the first factor and d/dB_d of the second:
+         * d/dC [(x-C)^i e^{-a (x-C)^2}] = -i (x-C)^(i-1) e + 2a (x-C)^(i+1) e */
+        double f = w * c->V[c->lvl_off[lv] + wflat] * cc;
+        double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+        for (int i = 0; i < na; ++i) {
+            for (int j = 0; j < nb; ++j) {
+                double Dij = c->D[(long)(mu0 + i) * c->n_ao + nu0 + j];
+                if (Dij == 0.0) return;
+                for (int d = 0; d < 3; ++d) {
+                    /* derivative of the first primitive along d */
+                    double da = 1.0, db = 1.0;
+                    for (int e = 0; e < 3; ++e) {
+                        int pa = ax[i][e], pb = bx[j][e];
+                        double va = ga[e][pa * n[e] + tt[e]];
+                        double vb = gb[e][pb * n[e] + tt[e]];
+                        if (e == d) {
+                            double dva = 2.0 * p->aa * ga[e][(pa + 1) * n[e] + tt[e]];
+                            if (pa > 0) dva -= pa * ga[e][(pa - 1) * n[e] + tt[e]];
+                            double dvb = 2.0 * p->ab * gb[e][(pb + 1) * n[e] + tt[e]];
+                            if (pb > 0) dvb -= pb * gb[e][(pb - 1) * n[e] + tt[e]];
+                            da *= dva * vb;
+                            db *= va * dvb;
+                        } else {
+                            da *= va * vb;
+                            db *= va * vb;
+                        }
+                    }
+                    gA[d] += Dij * da;
+                    gB[d] += Dij * db;
+                }
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            out[3 * p->atom_a + d] += f * gA[d];
+            out[3 * p->atom_b + d] += f * gB[d];
+        }
+    }
+}
+
+/* General cell: grid point i of a level at r = sum_d (i_d / N_d) a_d.  The
+ * truncation sphere is an ellipsoid in index space; the box of indices whose
+ * fractional coordinate can lie within R of P is visited point by point, and
+ * each primitive is tabulated at the point itself (its Cartesian factors
+ * x, y, z still separate), then the same per-point terms apply. */
+static void eval_pair_general(const osys *s, const opair *p, octx *c, int tid)
+{
+    const int lv = p->level;
+    const int *N = s->mesh + 3 * lv;
+    double inv[9];
+    const double det = fabs(lat_inverse(s->lat, inv));
+    const double w = det / ((double)N[0] * N[1] * N[2]);
+    long lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        double u = p->P[0] * inv[d] + p->P[1] * inv[3 + d] + p->P[2] * inv[6 + d];
+        double du = p->R * inv_col_norm(inv, d);
+        lo[d] = (long)ceil((u - du) * N[d]);
+        hi[d] = (long)floor((u + du) * N[d]);
+        if (hi[d] < lo[d]) return;
+    }
+    if (c->nsamp > 0 && lv != c->samp_level) return;
+    if ((c->mode == MODE_MAT || c->mode == MODE_MAT_TAU) && c->sp_slot &&
+        c->sp_slot[(long)p->sa * s->nshell + p->sb] < 0)
+        return;
+    const int la = p->la, lb = p->lb, na = ncart(la), nb = ncart(lb);
+    const int extra = c->mode == MODE_GRAD ? 1 : c->mode == MODE_TAU || c->mode == MODE_MAT_TAU ? 1
+                      : c->mode == MODE_GRAD_TAU ? 2 : 0;
+    const int ea = la + extra, eb = lb + extra;
+    int ax[OR_NCART][3], bx[OR_NCART][3];
+    for (int m = 0; m < na; ++m) cart_exps(la, m, &ax[m][0], &ax[m][1], &ax[m][2]);
+    for (int m = 0; m < nb; ++m) cart_exps(lb, m, &bx[m][0], &bx[m][1], &bx[m][2]);
+    double tga[3][OR_MAXL + 3], tgb[3][OR_MAXL + 3];
+    double *ga[3] = {tga[0], tga[1], tga[2]}, *gb[3] = {tgb[0], tgb[1], tgb[2]};
+    const long one[3] = {1, 1, 1}, zero[3] = {0, 0, 0};
+    const double R2 = p->R * p->R;
+    double *out = c->tbuf[tid];
+    long nvis = 0;
+    const long nlist = (c->nsamp > 0) ? c->nsamp : 1;
+    for (long sidx = 0; sidx < nlist; ++sidx) {
+        long ulo[3], ustep[3];
+        if (c->nsamp > 0) {
+            long f = c->samp_idx[sidx];
+            long wv[3] = {f / ((long)N[1] * N[2]), (f / N[2]) % N[1], f % N[2]};
+            for (int d = 0; d < 3; ++d) {
+                long u = wv[d] + N[d] * (long)ceil((double)(lo[d] - wv[d]) / N[d]);
+                while (u < lo[d]) u += N[d];
+                while (u - N[d] >= lo[d]) u -= N[d];
+                ulo[d] = u;
+                ustep[d] = N[d];
+            }
+        } else {
+            for (int d = 0; d < 3; ++d) { ulo[d] = lo[d]; ustep[d] = 1; }
+        }
+        for (long i0 = ulo[0]; i0 <= hi[0]; i0 += ustep[0])
+            for (long i1 = ulo[1]; i1 <= hi[1]; i1 += ustep[1])
+                for (long i2 = ulo[2]; i2 <= hi[2]; i2 += ustep[2]) {
+                    const double f0 = (double)i0 / N[0], f1 = (double)i1 / N[1], f2 = (double)i2 / N[2];
+                    double r[3], d2 = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        r[k] = f0 * s->lat[k] + f1 * s->lat[3 + k] + f2 * s->lat[6 + k];
+                        const double t = r[k] - p->P[k];
+                        d2 += t * t;
+                    }
+                    if (d2 > R2) continue;
+                    ++nvis;
+                    /* (x - C)^q exp(-a (x - C)^2) of each primitive at this point, per axis */
+                    for (int k = 0; k < 3; ++k) {
+                        double dx = r[k] - p->A[k], e = exp(-p->aa * dx * dx), pw = 1.0;
+                        for (int q = 0; q <= ea; ++q) { ga[k][q] = pw * e; pw *= dx; }
+                        dx = r[k] - p->B[k];
+                        e = exp(-p->ab * dx * dx);
+                        pw = 1.0;
+                        for (int q = 0; q <= eb; ++q) { gb[k][q] = pw * e; pw *= dx; }
+                    }
+                    const long wflat = (lmod(i0, N[0]) * N[1] + lmod(i1, N[1])) * N[2] + lmod(i2, N[2]);
+                    point_terms(s, c, p, ga, gb, one, zero, ax, bx, wflat, sidx, w, out);
+                }
+    }
+    c->counts[tid * OR_NCNT + 5 * la + lb] += nvis;
+}
+
 static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
 {
     octx *c = (octx *)vctx;
+    if (s->lat) {
+        eval_pair_general(s, p, c, tid);
+        return;
+    }
     const int lv = p->level;
     const int *N = s->mesh + 3 * lv;
     double h[3];
@@ -362,8 +616,6 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
     int ax[OR_NCART][3], bx[OR_NCART][3];
     for (int m = 0; m < na; ++m) cart_exps(la, m, &ax[m][0], &ax[m][1], &ax[m][2]);
     for (int m = 0; m < nb; ++m) cart_exps(lb, m, &bx[m][0], &bx[m][1], &bx[m][2]);
-    const int mu0 = c->ao_off[p->sa], nu0 = c->ao_off[p->sb];
-    const double cc = p->ca * p->cb;
     const double R2 = p->R * p->R;
     double *out = c->tbuf[tid];
     long nvis = 0;
@@ -400,125 +652,7 @@ static void eval_pair(const osys *s, const opair *p, void *vctx, int tid)
                     if (dx * dx + dy * dy + dz * dz > R2) continue;
                     ++nvis;
                     long wflat = (lmod(ux, N[0]) * N[1] + lmod(uy, N[1])) * N[2] + lmod(uz, N[2]);
-                    double Ga[OR_NCART], Gb[OR_NCART];
-                    for (int m = 0; m < na; ++m)
-                        Ga[m] = ga[0][ax[m][0] * n[0] + tx] * ga[1][ax[m][1] * n[1] + ty] *
-                                ga[2][ax[m][2] * n[2] + tz];
-                    for (int m = 0; m < nb; ++m)
-                        Gb[m] = gb[0][bx[m][0] * n[0] + tx] * gb[1][bx[m][1] * n[1] + ty] *
-                                gb[2][bx[m][2] * n[2] + tz];
-                    if (c->mode >= MODE_TAU) {
-                        long tt[3] = {tx, ty, tz};
-                        double Da[OR_NCART][3], Db[OR_NCART][3];   /* grad G along each axis */
-                        for (int m = 0; m < na; ++m)
-                            for (int d = 0; d < 3; ++d) Da[m][d] = cart_d1(ga, n, tt, ax[m], p->aa, d);
-                        for (int m = 0; m < nb; ++m)
-                            for (int d = 0; d < 3; ++d) Db[m][d] = cart_d1(gb, n, tt, bx[m], p->ab, d);
-                        if (c->mode == MODE_TAU) {
-                            double acc = 0.0;
-                            for (int i = 0; i < na; ++i)
-                                for (int j = 0; j < nb; ++j) {
-                                    double dot = Da[i][0] * Db[j][0] + Da[i][1] * Db[j][1] + Da[i][2] * Db[j][2];
-                                    acc += c->D[(long)(mu0 + i) * c->n_ao + nu0 + j] * dot;
-                                }
-                            if (c->nsamp > 0) out[sidx] += 0.5 * cc * acc;
-                            else out[c->lvl_off[lv] + wflat] += 0.5 * cc * acc;
-                        } else if (c->mode == MODE_MAT_TAU) {
-                            double f = 0.5 * w * c->V[c->lvl_off[lv] + wflat] * cc;
-                            for (int i = 0; i < na; ++i)
-                                for (int j = 0; j < nb; ++j) {
-                                    double dot = Da[i][0] * Db[j][0] + Da[i][1] * Db[j][1] + Da[i][2] * Db[j][2];
-                                    long o;
-                                    if (c->sp_slot) o = c->sp_slot[(long)p->sa * s->nshell + p->sb] + i * nb + j;
-                                    else o = (long)(mu0 + i) * c->n_ao + nu0 + j;
-                                    out[o] += f * dot;
-                                }
-                        } else {
-                            /* d/dA_e grad G_a = -d/dr_e grad G_a (G_a depends on r - A) */
-                            double f = 0.5 * w * c->V[c->lvl_off[lv] + wflat] * cc;
-                            double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-                            for (int i = 0; i < na; ++i)
-                                for (int j = 0; j < nb; ++j) {
-                                    double Dij = c->D[(long)(mu0 + i) * c->n_ao + nu0 + j];
-                                    if (Dij == 0.0) continue;
-                                    for (int e = 0; e < 3; ++e)
-                                        for (int d = 0; d < 3; ++d) {
-                                            gA[e] -= Dij * cart_d2(ga, n, tt, ax[i], p->aa, e, d) * Db[j][d];
-                                            gB[e] -= Dij * Da[i][d] * cart_d2(gb, n, tt, bx[j], p->ab, e, d);
-                                        }
-                                }
-                            for (int e = 0; e < 3; ++e) {
-                                out[3 * p->atom_a + e] += f * gA[e];
-                                out[3 * p->atom_b + e] += f * gB[e];
-                            }
-                        }
-                        continue;
-                    }
-                    if (c->mode == MODE_RHO) {
-                        double acc = 0.0;
-                        for (int i = 0; i < na; ++i) {
-                            double t = 0.0;
-                            for (int j = 0; j < nb; ++j)
-                                t += c->D[(long)(mu0 + i) * c->n_ao + nu0 + j] * Gb[j];
-                            acc += Ga[i] * t;
-                        }
-                        if (c->nsamp > 0) out[sidx] += cc * acc;
-                        else out[c->lvl_off[lv] + wflat] += cc * acc;
-                    } else if (c->mode == MODE_MAT) {
-                        double f = w * c->V[c->lvl_off[lv] + wflat] * cc;
-                        long base;
-                        long stride;
-                        if (c->sp_slot) {
-                            base = c->sp_slot[(long)p->sa * s->nshell + p->sb];
-                            if (base < 0) continue;
-                            stride = nb;
-                            for (int i = 0; i < na; ++i)
-                                for (int j = 0; j < nb; ++j)
-                                    out[base + i * stride + j] += f * Ga[i] * Gb[j];
-                        } else {
-                            for (int i = 0; i < na; ++i)
-                                for (int j = 0; j < nb; ++j)
-                                    out[(long)(mu0 + i) * c->n_ao + nu0 + j] += f * Ga[i] * Gb[j];
-                        }
-                    } else {
-                        /* d/dA_d of the first factor and d/dB_d of the second:
-                         * d/dC [(x-C)^i e^{-a (x-C)^2}] = -i (x-C)^(i-1) e + 2a (x-C)^(i+1) e */
-                        double f = w * c->V[c->lvl_off[lv] + wflat] * cc;
-                        double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-                        long tt[3] = {tx, ty, tz};
-                        for (int i = 0; i < na; ++i) {
-                            for (int j = 0; j < nb; ++j) {
-                                double Dij = c->D[(long)(mu0 + i) * c->n_ao + nu0 + j];
-                                if (Dij == 0.0) continue;
-                                for (int d = 0; d < 3; ++d) {
-                                    /* derivative of the first primitive along d */
-                                    double da = 1.0, db = 1.0;
-                                    for (int e = 0; e < 3; ++e) {
-                                        int pa = ax[i][e], pb = bx[j][e];
-                                        double va = ga[e][pa * n[e] + tt[e]];
-                                        double vb = gb[e][pb * n[e] + tt[e]];
-                                        if (e == d) {
-                                            double dva = 2.0 * p->aa * ga[e][(pa + 1) * n[e] + tt[e]];
-                                            if (pa > 0) dva -= pa * ga[e][(pa - 1) * n[e] + tt[e]];
-                                            double dvb = 2.0 * p->ab * gb[e][(pb + 1) * n[e] + tt[e]];
-                                            if (pb > 0) dvb -= pb * gb[e][(pb - 1) * n[e] + tt[e]];
-                                            da *= dva * vb;
-                                            db *= va * dvb;
-                                        } else {
-                                            da *= va * vb;
-                                            db *= va * vb;
-                                        }
-                                    }
-                                    gA[d] += Dij * da;
-                                    gB[d] += Dij * db;
-                                }
-                            }
-                        }
-                        for (int d = 0; d < 3; ++d) {
-                            out[3 * p->atom_a + d] += f * gA[d];
-                            out[3 * p->atom_b + d] += f * gB[d];
-                        }
-                    }
+                    point_terms(s, c, p, ga, gb, n, (const long[3]){tx, ty, tz}, ax, bx, wflat, sidx, w, out);
                 }
             }
         }

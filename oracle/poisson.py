@@ -18,7 +18,9 @@ FFTs of numpy (FP64) and one loop over levels:
 
 The coefficients of all levels live on the plane-wave set of the finest mesh
 (level 0 holds the finest mesh); a level's masked plane wave m lands on the
-fine-grid index m mod N_0.  Orthorhombic cell (side lengths L).
+fine-grid index m mod N_0.  The cell is given by its side lengths L
+(orthorhombic) or its lattice vectors as rows (general cell: G = sum_d m_d b_d
+with b_d = 2 pi (A^-1)[:, d]).
 """
 from __future__ import annotations
 
@@ -34,23 +36,39 @@ def _freqs(n):
     return np.concatenate([np.arange(0, (n + 1) // 2), np.arange(-(n // 2), 0)]).astype(np.int64)
 
 
+def lattice(L):
+    """Lattice vectors as rows: diag(L) for side lengths L, or L itself (3 x 3)."""
+    L = np.asarray(L, dtype=np.float64)
+    return np.diag(L.reshape(3)) if L.size == 3 else L.reshape(3, 3)
+
+
+def gcart(L, mx, my, mz):
+    """Cartesian components of G = sum_d m_d b_d, b_d = 2 pi (A^-1)[:, d] (A: the
+    lattice vectors as rows, so that G . r = 2 pi m . u for r = u A)."""
+    b = 2 * math.pi * np.linalg.inv(lattice(L))     # column d is b_d
+    return [mx * b[c, 0] + my * b[c, 1] + mz * b[c, 2] for c in range(3)]
+
+
+def volume(L):
+    return float(abs(np.linalg.det(lattice(L))))
+
+
 def level_mask(L, mesh, cutoff_ry):
     """Boolean mask over a level's FFT grid: no Nyquist plane, |G|^2 < E_l."""
     m = [_freqs(n) for n in mesh]
     mx, my, mz = np.meshgrid(*m, indexing="ij")
     ok = (np.abs(mx) < mesh[0] / 2.0) & (np.abs(my) < mesh[1] / 2.0) & (np.abs(mz) < mesh[2] / 2.0)
     if cutoff_ry is not None:
-        g2 = ((2 * math.pi * mx / L[0]) ** 2 + (2 * math.pi * my / L[1]) ** 2 +
-              (2 * math.pi * mz / L[2]) ** 2)
-        ok &= g2 < cutoff_ry
+        g = gcart(L, mx, my, mz)
+        ok &= g[0] ** 2 + g[1] ** 2 + g[2] ** 2 < cutoff_ry
     return ok, (mx, my, mz)
 
 
 def poisson(L, meshes, cutoffs_ry, rho):
     """(v_l per level, E_J) from the level densities rho_l (C-ordered grids).
-    cutoffs_ry: per level cutoff in Ry, or None for every plane wave."""
-    L = np.asarray(L, dtype=np.float64).reshape(3)
-    vol = float(np.prod(L))
+    L: side lengths (3,) or lattice vectors as rows (3 x 3); cutoffs_ry: per
+    level cutoff in Ry, or None for every plane wave."""
+    vol = volume(L)
     fine = tuple(int(x) for x in meshes[0])
     acc = np.zeros(fine, dtype=np.complex128)
     masks = []
@@ -64,8 +82,9 @@ def poisson(L, meshes, cutoffs_ry, rho):
         iz = np.mod(mz[ok], fine[2])
         np.add.at(acc, (ix, iy, iz), f[ok])
         masks.append((ok, ix, iy, iz))
-    gx, gy, gz = [2 * math.pi * _freqs(n) / L[d] for d, n in enumerate(fine)]
-    g2 = gx[:, None, None] ** 2 + gy[None, :, None] ** 2 + gz[None, None, :] ** 2
+    fx, fy, fz = np.meshgrid(*[_freqs(n) for n in fine], indexing="ij")
+    g = gcart(L, fx, fy, fz)
+    g2 = g[0] ** 2 + g[1] ** 2 + g[2] ** 2
     coul = np.zeros(fine)
     coul[g2 > 0] = 4 * math.pi / g2[g2 > 0]
     vt = acc * coul
@@ -83,8 +102,7 @@ def poisson(L, meshes, cutoffs_ry, rho):
 
 def _fine_coefficients(L, meshes, cutoffs_ry, rho):
     """rho~ on the finest mesh's plane waves and the level masks / fine indices."""
-    L = np.asarray(L, dtype=np.float64).reshape(3)
-    vol = float(np.prod(L))
+    vol = volume(L)
     fine = tuple(int(x) for x in meshes[0])
     acc = np.zeros(fine, dtype=np.complex128)
     masks = []
@@ -100,7 +118,9 @@ def _fine_coefficients(L, meshes, cutoffs_ry, rho):
 
 
 def _gvectors(L, fine):
-    return [2 * math.pi * _freqs(n).astype(np.float64) / L[d] for d, n in enumerate(fine)]
+    """The Cartesian components of G on the fine FFT grid (full arrays)."""
+    fx, fy, fz = np.meshgrid(*[_freqs(n) for n in fine], indexing="ij")
+    return gcart(L, fx, fy, fz)
 
 
 def fine_density(L, meshes, cutoffs_ry, rho):
@@ -112,9 +132,8 @@ def fine_density(L, meshes, cutoffs_ry, rho):
     acc, _, L, vol, fine = _fine_coefficients(L, meshes, cutoffs_ry, rho)
     n0 = float(np.prod(fine))
     g = _gvectors(L, fine)
-    shape = [(fine[0], 1, 1), (1, fine[1], 1), (1, 1, fine[2])]
     rf = np.real(np.fft.ifftn(acc)) * (n0 / vol)
-    grad = [np.real(np.fft.ifftn(1j * g[d].reshape(shape[d]) * acc)) * (n0 / vol) for d in range(3)]
+    grad = [np.real(np.fft.ifftn(1j * g[d] * acc)) * (n0 / vol) for d in range(3)]
     return rf, grad
 
 
@@ -132,8 +151,7 @@ def hxc_potential(L, meshes, cutoffs_ry, rho, vxc=None, vxc_grad=None):
     n0 = float(np.prod(fine))
     w0 = vol / n0
     g = _gvectors(L, fine)
-    shape = [(fine[0], 1, 1), (1, fine[1], 1), (1, 1, fine[2])]
-    g2 = g[0].reshape(shape[0]) ** 2 + g[1].reshape(shape[1]) ** 2 + g[2].reshape(shape[2]) ** 2
+    g2 = g[0] ** 2 + g[1] ** 2 + g[2] ** 2
     coul = np.zeros(fine)
     coul[g2 > 0] = 4 * math.pi / g2[g2 > 0]
     vt = acc * coul
@@ -144,7 +162,7 @@ def hxc_potential(L, meshes, cutoffs_ry, rho, vxc=None, vxc_grad=None):
         vt = vt + ok0 * w0 * np.fft.fftn(np.asarray(vxc, dtype=np.float64).reshape(fine))
     if vxc_grad is not None:
         for d in range(3):
-            vt = vt - ok0 * 1j * g[d].reshape(shape[d]) * w0 * np.fft.fftn(
+            vt = vt - ok0 * 1j * g[d] * w0 * np.fft.fftn(
                 np.asarray(vxc_grad[d], dtype=np.float64).reshape(fine))
     out = []
     for l, mesh in enumerate(meshes):

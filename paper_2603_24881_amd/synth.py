@@ -43,7 +43,7 @@ class System:
     cutoffs and screening threshold."""
 
     name: str
-    cell: np.ndarray                  # (3,) orthorhombic side lengths
+    cell: np.ndarray                  # (3,) orthorhombic side lengths, or (3, 3) lattice vectors as rows
     coords: np.ndarray                # (natm, 3)
     shell_atom: np.ndarray            # (nshell,) int32
     shell_l: np.ndarray               # (nshell,) int32, 0..4
@@ -146,7 +146,8 @@ def assemble(name, cell, coords, atom_basis, **kw) -> System:
             p0 += len(e)
     return System(
         name=name,
-        cell=np.asarray(cell, dtype=np.float64).reshape(3),
+        cell=(np.asarray(cell, dtype=np.float64).reshape(3, 3) if np.size(cell) == 9
+              else np.asarray(cell, dtype=np.float64).reshape(3)),
         coords=np.asarray(coords, dtype=np.float64).reshape(-1, 3),
         shell_atom=np.asarray(sa, dtype=np.int32),
         shell_l=np.asarray(sl, dtype=np.int32),

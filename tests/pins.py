@@ -32,19 +32,31 @@ def cart_list(l):
     return out
 
 
+def lattice(cell):
+    """Lattice vectors as rows (3 x 3) of a (3,) orthorhombic cell or a 3 x 3 matrix."""
+    cell = np.asarray(cell, dtype=np.float64)
+    return np.diag(cell) if cell.shape == (3,) else cell
+
+
 def _images(cell, nimg):
     r = range(-nimg, nimg + 1)
-    return [np.array([i, j, k], dtype=np.float64) * cell for i in r for j in r for k in r]
+    a = lattice(cell)
+    return [np.array([i, j, k], dtype=np.float64) @ a for i in r for j in r for k in r]
+
+
+def grid_points(cell, mesh):
+    """Points of the C-ordered grid: r = sum_d (i_d / N_d) a_d."""
+    a = lattice(cell)
+    n = np.asarray(mesh)
+    ax = [np.arange(n[d]) / n[d] for d in range(3)]
+    U = np.stack(np.meshgrid(*ax, indexing="ij"), axis=-1).reshape(-1, 3)
+    return U @ a
 
 
 def brute_chi(sys, mesh, nimg=2):
     """chi[mu, point] on the C-ordered grid of ``mesh`` (no truncation)."""
     cell = np.asarray(sys.cell, dtype=np.float64)
-    n = np.asarray(mesh)
-    h = cell / n
-    ax = [np.arange(n[d]) * h[d] for d in range(3)]
-    X, Y, Z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
-    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    pts = grid_points(cell, mesh)
     chis = []
     for s in range(sys.nshell):
         l = int(sys.shell_l[s])
@@ -212,11 +224,7 @@ def brute_grad_chi(sys, mesh, nimg=2):
     r-derivative of x^i y^j z^k exp(-a r^2) is (i x^(i-1) - 2 a x^(i+1)) y^j z^k
     exp(-a r^2) along x, lattice-summed like ``brute_chi``."""
     cell = np.asarray(sys.cell, dtype=np.float64)
-    n = np.asarray(mesh)
-    h = cell / n
-    ax = [np.arange(n[d]) * h[d] for d in range(3)]
-    X, Y, Z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
-    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    pts = grid_points(cell, mesh)
     out = []
     for s in range(sys.nshell):
         l = int(sys.shell_l[s])

@@ -14,7 +14,10 @@ def tiny_system(shell_ls=(0, 1, 2, 3), natm=3, cell=(7.0, 8.0, 9.0), exp_range=(
     own randomly drawn shells of the given angular momenta."""
     rng = np.random.default_rng(seed)
     cell = np.asarray(cell, dtype=np.float64)
-    coords = rng.uniform(0.0, 1.0, size=(natm, 3)) * cell
+    if cell.shape == (3, 3):            # lattice vectors as rows
+        coords = rng.uniform(0.0, 1.0, size=(natm, 3)) @ cell
+    else:
+        coords = rng.uniform(0.0, 1.0, size=(natm, 3)) * cell
     basis = [synth.draw_element_basis(rng, list(shell_ls), exp_range, nprim=nprim)
              for _ in range(natm)]
     return synth.assemble(name, cell, coords, basis,
