@@ -20,8 +20,11 @@
  * Conventions shared by all calls
  * -------------------------------
  * Units: bohr, bohr^-2 for exponents, Rydberg for plane-wave cutoffs.
- * Cell: orthorhombic; lattice vectors are the rows of a[3][3] and must be
- *   diagonal (non-orthogonal cells return GPW_EUNSUPPORTED).
+ * Cell: lattice vectors a_d are the rows of a[3][3], right- or left-handed,
+ *   linearly independent.  A diagonal a is an orthorhombic cell; any other a
+ *   is a general (non-orthogonal) cell, evaluated in the grid-index
+ *   coordinates of each level with the cross terms of the Gaussian envelope
+ *   (appendix on non-orthogonal lattices).
  * Basis: contracted Cartesian shells, l = 0..4.  exps/coefs are the primitive
  *   exponents and raw coefficients: a contracted AO is
  *   sum_k coefs[k] (x-Ax)^i (y-Ay)^j (z-Az)^k exp(-exps[k] |r-A|^2)
@@ -31,8 +34,9 @@
  *   xx xy xz yy yz zz; xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz.
  * Matrices: n_ao x n_ao, row-major, FP64, device memory.
  * Grids: level l holds mesh[l][0]*mesh[l][1]*mesh[l][2] FP64 values in C
- *   order [i0][i1][i2]; point (i0,i1,i2) sits at (i0 h0, i1 h1, i2 h2) with
- *   h_d = L_d / mesh[l][d] (origin at the cell corner).
+ *   order [i0][i1][i2]; point (i0,i1,i2) sits at sum_d (i_d / mesh[l][d]) a_d
+ *   (origin at the cell corner; (i0 h0, i1 h1, i2 h2) with h_d = L_d / mesh[l][d]
+ *   for an orthorhombic cell of side lengths L_d).
  * Quadrature weight of level l: w_l = Omega / N_l (Sec. III.A, the weight in
  *   the definition of the V tensor).  eval_mat and eval_grad apply it; rho is
  *   unweighted.
@@ -46,7 +50,8 @@
  * Levels: a pair image goes to the coarsest level i with
  *   ke_cutoff_ry[i] >= alpha_p * rel_cutoff_ry, or to level 0 (finest) when
  *   none qualifies (Sec. II, multigrid).  Default mesh of a level: per axis the
- *   smallest 2,3,5-smooth N >= sqrt(E) L / pi.
+ *   smallest 2,3,5-smooth N >= sqrt(E) |a_d| / pi, so that every plane wave
+ *   with |G|^2 < E has |m_d| = |G . a_d| / (2 pi) < N / 2.
  *
  * Errors: every call returns a gpw_status.  Argument errors are detected
  * before anything is enqueued.  A device fault surfaces as GPW_EDEVICE on a
@@ -75,10 +80,10 @@ extern "C" {
 typedef enum {
     GPW_OK = 0,
     GPW_EINVAL = 1,        /* bad argument (NULL pointer, l < 0, exponent <= 0, ...) */
-    GPW_EUNSUPPORTED = 2,  /* valid but not implemented (non-orthogonal cell, g shells) */
+    GPW_EUNSUPPORTED = 2,  /* valid but not implemented (l > 4, a truncation sphere too wide) */
     GPW_ENOMEM = 3,        /* device allocation failed */
     GPW_EDEVICE = 4,       /* HIP runtime error or device fault */
-    GPW_EBUDGET = 5        /* the request does not fit the caller's memory budget */
+    GPW_EBUDGET = 5        /* the call's scratch does not fit a fixed budget (gpw_eval_mat_noalloc) */
 } gpw_status;
 
 typedef enum { GPW_FP64 = 0, GPW_FP32 = 1 } gpw_precision;
@@ -161,7 +166,8 @@ typedef struct {
  * (Sec. III.B; appendix on GTO screening, Algs. 4 and 5).  All host inputs
  * are copied; the caller may free them on return.  The plan owns its device
  * memory on cut->device.  Synchronous.  Errors: GPW_EINVAL for NULL or invalid
- * arguments, GPW_EUNSUPPORTED for a non-diagonal cell, l > 4, or a truncation
+ * arguments (including linearly dependent lattice vectors), GPW_EUNSUPPORTED
+ * for l > 4, or a truncation
  * sphere too wide for the kernels (more than 1024 points per axis, more than
  * 127 cell periods, or point tables beyond one workgroup's LDS), GPW_ENOMEM,
  * GPW_EDEVICE. */
@@ -221,7 +227,9 @@ gpw_status gpw_eval_grad_tau(gpw_plan_t plan, const double *D, const double *con
 /* Multigrid Fourier transfer and Poisson solve (Sec. II: the Hartree
  * potential of Eqs. (vH), (vHG) and the multigrid Fourier interpolation
  * between the levels), the step between gpw_eval_rho and gpw_eval_mat of a
- * Fock build.  With w_l = Omega / N_l, plane waves G = 2 pi m / L, and
+ * Fock build.  With w_l = Omega / N_l, plane waves G = sum_d m_d b_d with
+ * integer m and the reciprocal vectors b_d = 2 pi (A^-1)[:, d] (G = 2 pi m / L
+ * for an orthorhombic cell), and
  * mask_l(G) = {|m_d| < N_{l,d} / 2 on every axis and |G|^2 < E_l (Ry, bohr^-2)}
  * (every non-Nyquist plane wave for a single-level plan built from a mesh):
  *   rho~(G) = sum_l mask_l(G) w_l sum_r rho_l(r) exp(-i G.r)
@@ -281,11 +289,18 @@ typedef struct {
     double *out;                 /* MAT, MAT_TAU: M (n_ao x n_ao); GRAD, GRAD_TAU: natm x 3 */
 } gpw_task;
 
-/* Batched evaluation for serving: the tasks, possibly of different plans, run
- * as one set of persistent launches that pull work items from a shared queue,
- * so that the work of several requests overlaps on the device.  Each task
- * computes exactly what the corresponding single call computes.  Outputs of
- * different tasks must not overlap.  Enqueued on stream. */
+/* Batched evaluation for serving: the tasks, possibly of different plans and
+ * operations, share launches so that the work of several requests overlaps on
+ * the device.  Per (operation, (l_a, l_b) class) one launch covers the
+ * (task, level) segments of every task, described by a segment table passed
+ * by value (at most 16 segments per launch; more segments take more
+ * launches); the hardware dispatcher deals each launch's workgroups to the
+ * compute units as they free up.  FP64 and FP32 plans form two such sets of
+ * launches, back to back.  A single call is a batch of one task: each task
+ * computes exactly what the corresponding single call computes (rho and tau
+ * bit for bit; matrices and gradients up to the order of their atomic
+ * additions).  The scratch of all tasks is one stream-ordered allocation.
+ * Outputs of different tasks must not overlap.  Enqueued on stream. */
 gpw_status gpw_eval_batch(const gpw_task *tasks, int ntasks, void *stream);
 
 /* gpw_eval_mat without any device allocation, for callers that cannot

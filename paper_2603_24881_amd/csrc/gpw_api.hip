@@ -53,6 +53,80 @@ struct DeviceGuard {
     }
 };
 
+// Inverse and determinant of a 3 x 3 matrix.
+double inverse3(const double a[3][3], double inv[3][3])
+{
+    const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                       a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                       a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+            inv[i][j] = (a[i1][j1] * a[i2][j2] - a[i1][j2] * a[i2][j1]) / det;
+        }
+    return det;
+}
+
+// Smallest eigenvalue of a symmetric positive definite 3 x 3 matrix (cyclic
+// Jacobi rotations).
+double min_eigenvalue(const double m[3][3])
+{
+    double a[3][3];
+    std::memcpy(a, m, sizeof(a));
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        if (off < 1e-30 * (a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2])) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double th = 0.5 * std::atan2(2.0 * a[p][q], a[q][q] - a[p][p]);
+                const double c = std::cos(th), s = std::sin(th);
+                for (int k = 0; k < 3; ++k) {   // columns
+                    const double akp = a[k][p], akq = a[k][q];
+                    a[k][p] = c * akp - s * akq;
+                    a[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < 3; ++k) {   // rows
+                    const double apk = a[p][k], aqk = a[q][k];
+                    a[p][k] = c * apk - s * aqk;
+                    a[q][k] = s * apk + c * aqk;
+                }
+            }
+    }
+    return std::min(a[0][0], std::min(a[1][1], a[2][2]));
+}
+
+// T_n of a level: the coefficients of (r - A)^m, r - A = s H, as a polynomial
+// in the index offset s (ncart(n) x ncart(n), row m, column k, both in shell
+// order), by multiplying out one linear factor (s H)_c at a time.
+void monomial_transform(const double H[3][3], int n, double *T)
+{
+    const int nc = ncart(n);
+    auto idx = [](int ly, int lz) { return (ly + lz) * (ly + lz + 1) / 2 + lz; };
+    int m = 0;
+    for (int mx = n; mx >= 0; --mx)
+        for (int my = n - mx; my >= 0; --my, ++m) {
+            const int me[3] = {mx, my, n - mx - my};
+            std::vector<double> poly(1, 1.0), next;
+            int deg = 0;
+            for (int c = 0; c < 3; ++c)
+                for (int rep = 0; rep < me[c]; ++rep) {
+                    next.assign(ncart(deg + 1), 0.0);
+                    int k = 0;
+                    for (int kx = deg; kx >= 0; --kx)
+                        for (int ky = deg - kx; ky >= 0; --ky, ++k) {
+                            const int kz = deg - kx - ky;
+                            next[idx(ky, kz)] += poly[k] * H[0][c];       // s_x h_x,c
+                            next[idx(ky + 1, kz)] += poly[k] * H[1][c];   // s_y h_y,c
+                            next[idx(ky, kz + 1)] += poly[k] * H[2][c];   // s_z h_z,c
+                        }
+                    poly.swap(next);
+                    ++deg;
+                }
+            for (int k = 0; k < nc; ++k) T[(size_t)m * nc + k] = poly[k];
+        }
+}
+
 void free_plan(gpw_plan_s *pl)
 {
     if (!pl) return;
@@ -73,19 +147,23 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
     if (!out) return fail(GPW_EINVAL, "gpw_plan: out is NULL");
     *out = nullptr;
     if (!cell || !basis || !cut) return fail(GPW_EINVAL, "gpw_plan: NULL cell, basis or cutoffs");
-    // ---- cell
-    double L[3];
+    // ---- cell: a diagonal matrix is orthorhombic, anything else a general cell
+    double L[3], Alat[3][3], Ainv[3][3];
+    int tri = 0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             const double a = cell->a[i][j];
             if (!std::isfinite(a)) return fail(GPW_EINVAL, "gpw_plan: non-finite lattice vector");
-            if (i != j && a != 0.0)
-                return fail(GPW_EUNSUPPORTED, "gpw_plan: only orthorhombic (diagonal) cells are supported");
+            Alat[i][j] = a;
+            if (i != j && a != 0.0) tri = 1;
         }
     for (int d = 0; d < 3; ++d) {
-        L[d] = cell->a[d][d];
-        if (!(L[d] > 0.0)) return fail(GPW_EINVAL, "gpw_plan: lattice lengths must be positive");
+        L[d] = std::sqrt(Alat[d][0] * Alat[d][0] + Alat[d][1] * Alat[d][1] + Alat[d][2] * Alat[d][2]);
+        if (!tri && !(Alat[d][d] > 0.0)) return fail(GPW_EINVAL, "gpw_plan: lattice lengths must be positive");
     }
+    const double det = inverse3(Alat, Ainv);
+    if (!(std::fabs(det) > 1e-6 * L[0] * L[1] * L[2]))
+        return fail(GPW_EINVAL, "gpw_plan: lattice vectors are (nearly) linearly dependent");
     // ---- basis
     const gpw_basis &B = *basis;
     if (B.natm < 1 || B.nshell < 1) return fail(GPW_EINVAL, "gpw_plan: need at least one atom and one shell");
@@ -143,7 +221,12 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
     pl->tau = C.tau;
     pl->rel_cut = C.rel_cutoff_ry;
     for (int d = 0; d < 3; ++d) pl->L[d] = L[d];
-    const double vol = L[0] * L[1] * L[2];
+    pl->tri = tri;
+    std::memcpy(pl->A, Alat, sizeof(Alat));
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) pl->recip[d][c] = 2.0 * M_PI * Ainv[c][d];
+    const double vol = std::fabs(det);
+    pl->volume = vol;
     for (int l = 0; l < C.nlevels; ++l) {
         LevelGeom &G = pl->geom[l];
         pl->cut_ry[l] = C.ke_cutoff_ry ? C.ke_cutoff_ry[l] : 0.0;
@@ -153,17 +236,33 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
                 n = C.mesh[3 * l + d];
                 if (n < 1 || n > (1 << 20)) { free_plan(pl); return fail(GPW_EINVAL, "gpw_plan: mesh out of range"); }
             } else {
+                // |a_d| = L[d]: a plane wave with |G|^2 < E has
+                // |m_d| = |G . a_d| / (2 pi) < sqrt(E) |a_d| / (2 pi) <= N / 2
                 n = (long)std::ceil(std::sqrt(C.ke_cutoff_ry[l]) * L[d] / M_PI);
                 if (n < 1) n = 1;
                 while (!smooth235(n)) ++n;
             }
             G.N[d] = (int)n;
             G.nb[d] = (int)((n + 3) / 4);
-            G.h[d] = L[d] / (double)n;
+            G.h[d] = tri ? 1.0 : L[d] / (double)n;   // index units for a general cell
         }
         pl->ngrid[l] = (long long)G.N[0] * G.N[1] * G.N[2];
         pl->nblocks[l] = (long long)G.nb[0] * G.nb[1] * G.nb[2];
         G.w = vol / (double)pl->ngrid[l];
+        G.tri = nullptr;
+        if (tri) {
+            TriGeom &t = pl->tri_host[l];
+            for (int d = 0; d < 3; ++d)
+                for (int c = 0; c < 3; ++c) t.H[d][c] = Alat[d][c] / G.N[d];
+            inverse3(t.H, t.Hinv);
+            for (int d = 0; d < 3; ++d)
+                for (int e2 = 0; e2 < 3; ++e2)
+                    t.g[d][e2] = t.H[d][0] * t.H[e2][0] + t.H[d][1] * t.H[e2][1] + t.H[d][2] * t.H[e2][2];
+            t.lmin = min_eigenvalue(t.g) * (1.0 - 1e-9);   // a hair below: the bound stays conservative
+            for (int d = 0; d < 3; ++d)
+                t.rf[d] = std::sqrt(t.Hinv[0][d] * t.Hinv[0][d] + t.Hinv[1][d] * t.Hinv[1][d] +
+                                    t.Hinv[2][d] * t.Hinv[2][d]);
+        }
     }
 
     // primitive-shell table (host flattening of the basis arrays)
@@ -222,7 +321,40 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
     }
     PartitionInput in;
     in.ps = PsTable{pl->d_ps_atom, pl->d_ps_l, pl->d_ps_ao, pl->d_ps_alpha, pl->d_ps_coef, pl->d_coords, n_ps};
+    if (tri) {
+        // the levels' transforms T_n and geometry records on the device
+        size_t per = 0;
+        int toff[kMaxTDeg + 1];
+        for (int n2 = 0; n2 <= kMaxTDeg; ++n2) {
+            toff[n2] = (int)per;
+            per += (size_t)ncart(n2) * ncart(n2);
+        }
+        std::vector<double> T(per * C.nlevels);
+        for (int l = 0; l < C.nlevels; ++l)
+            for (int n2 = 0; n2 <= kMaxTDeg; ++n2) monomial_transform(pl->tri_host[l].H, n2, &T[l * per + toff[n2]]);
+        double *dT = nullptr;
+        if ((e = upload(dT, T)) != hipSuccess) {
+            (void)hipStreamDestroy(st);
+            free_plan(pl);
+            return hip_fail(e, "gpw_plan: upload");
+        }
+        std::vector<TriGeom> tg(C.nlevels);
+        for (int l = 0; l < C.nlevels; ++l) {
+            pl->tri_host[l].T = dT + l * per;
+            std::memcpy(pl->tri_host[l].toff, toff, sizeof(toff));
+            tg[l] = pl->tri_host[l];
+        }
+        if ((e = upload(pl->d_tri, tg)) != hipSuccess) {
+            (void)hipStreamDestroy(st);
+            free_plan(pl);
+            return hip_fail(e, "gpw_plan: upload");
+        }
+        for (int l = 0; l < C.nlevels; ++l) pl->geom[l].tri = pl->d_tri + l;
+    }
     for (int d = 0; d < 3; ++d) in.pc.L[d] = L[d];
+    in.pc.tri = tri;
+    std::memcpy(in.pc.A, Alat, sizeof(Alat));
+    std::memcpy(in.pc.Ainv, Ainv, sizeof(Ainv));
     in.pc.logtau = std::log(C.tau);
     in.pc.rel_cut = C.rel_cutoff_ry;
     in.pc.nlevels = C.nlevels;
@@ -248,7 +380,7 @@ gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis, const gpw_cuto
         int lds_max = 0;
         (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
         const size_t need = gpw::pair_kernel_lds_bytes(pl->max_axis_blocks > 0 ? pl->max_axis_blocks : 1,
-                                                       pl->precision);
+                                                       pl->precision, pl->tri != 0);
         if (lds_max > 0 && need > (size_t)lds_max) {
             const std::string msg = "gpw_plan: the widest truncation sphere (" +
                                     std::to_string(pl->info.max_box_width) + " points per axis) needs " +

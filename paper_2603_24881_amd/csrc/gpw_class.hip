@@ -19,12 +19,23 @@ static void launch_lists(const ClassLaunch &cl)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     const hipStream_t st = cl.st;
-    const size_t smem = cl.smem;
+    const size_t smem = cl.smem, smem_t = cl.smem_t;
+    // packed coefficients (general cells: Cartesian tensors, then their
+    // rewrite on the index offset)
     cl.packs.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
         if constexpr (rho_tensor(LA, LB))
             hipLaunchKernelGGL((k_pack_density<T, LA, LB>), dim3(g), dim3(256), 0, st, tb);
         else
             hipLaunchKernelGGL((k_pack_direct<T, NA, NB>), dim3(g), dim3(256), 0, st, tb);
+    }, false);
+    cl.packs_t.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_pack_density<T, LA, LB>), dim3(g), dim3(256), 0, st, tb);
+    }, false);
+    cl.tpacks.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_pack_tau<T, LA, LB>), dim3(g), dim3(256), 0, st, tb);
+    }, false);
+    cl.idxs.launch([&](const SegTable<IdxSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_to_index<T>), dim3(g), dim3(256), 0, st, tb);
     }, false);
     using RS = RhoSplit<LA, LB>;
     cl.rhos.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
@@ -34,24 +45,39 @@ static void launch_lists(const ClassLaunch &cl)
             hipLaunchKernelGGL((k_rho<LA, LB, RS::npass, RS::wpe, RS::stage, RS::pref, T>), dim3(g), dim3(64), 0, st,
                                tb);
     }, true);
+    cl.rhos_t.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_rho_tri<LA, LB, TauSplit<LA + LB>::npass, T>), dim3(g), dim3(64), 0, st, tb);
+    }, true);
     cl.mats.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
         hipLaunchKernelGGL((k_mat<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
+    }, true);
+    cl.mats_t.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_mat<LA, LB, T, true>), dim3(g), dim3(64), smem_t, st, tb);
     }, true);
     cl.grads.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
         hipLaunchKernelGGL((k_grad<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
     }, true);
-    cl.tpacks.launch([&](const SegTable<PackSeg> &tb, unsigned g) {
-        hipLaunchKernelGGL((k_pack_tau<T, LA, LB>), dim3(g), dim3(256), 0, st, tb);
-    }, false);
+    cl.grads_t.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_grad<LA, LB, T, true>), dim3(g), dim3(64), smem_t, st, tb);
+    }, true);
     using TS = TauSplit<LA + LB + 2>;
     cl.taus.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
         hipLaunchKernelGGL((k_tau<LA, LB, TS::npass, TS::wpe, T>), dim3(g), dim3(64), 0, st, tb);
     }, true);
+    cl.taus_t.launch([&](const SegTable<RhoSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_tau_tri<LA, LB, TS::npass, T>), dim3(g), dim3(64), 0, st, tb);
+    }, true);
     cl.mtaus.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
         hipLaunchKernelGGL((k_mat_tau<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
     }, true);
+    cl.mtaus_t.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_mat_tau<LA, LB, T, true>), dim3(g), dim3(64), smem_t, st, tb);
+    }, true);
     cl.gtaus.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
         hipLaunchKernelGGL((k_grad_tau<LA, LB, T>), dim3(g), dim3(64), smem, st, tb);
+    }, true);
+    cl.gtaus_t.launch([&](const SegTable<PairSeg> &tb, unsigned g) {
+        hipLaunchKernelGGL((k_grad_tau<LA, LB, T, true>), dim3(g), dim3(64), smem_t, st, tb);
     }, true);
 }
 

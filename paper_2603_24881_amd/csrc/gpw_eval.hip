@@ -91,7 +91,9 @@ static long long block_copy_blocks(const gpw_plan_s *pl, int l)
 // Scratch of one task inside the batch's stream-ordered allocation.
 struct TaskScratch {
     size_t dpk = 0, ds = 0, vb = 0;      // byte offsets
+    size_t tmp = 0;                      // general cells: Cartesian coefficient tensors (FP64)
     long long dbase[kMaxGroups + 1];     // packed-D offsets of the groups (elements)
+    long long tbase[kMaxGroups + 1];     // their offsets in tmp (doubles)
     long long voff[kMaxLevels];          // block-grid offsets of the levels (doubles)
 };
 
@@ -107,14 +109,22 @@ static size_t task_scratch(const gpw_plan_s *pl, int op, size_t base, TaskScratc
 {
     size_t bytes = base;
     if (grid_op(op)) {
+        const bool tri = pl->tri != 0;
         x.dbase[0] = 0;
+        x.tbase[0] = 0;
         for (int g = 0; g < kMaxGroups; ++g) {
             const int c = g % kNCls;
-            x.dbase[g + 1] = x.dbase[g] + (pl->group_off[g + 1] - pl->group_off[g]) *
-                                              cstride<T>(grid_ncoef(cls_la(c), cls_lb(c), extra_degree(op)));
+            const long long np = pl->group_off[g + 1] - pl->group_off[g];
+            const int K = grid_ncoef(cls_la(c), cls_lb(c), extra_degree(op), tri);
+            x.dbase[g + 1] = x.dbase[g] + np * cstride<T>(K);
+            x.tbase[g + 1] = x.tbase[g] + (tri ? np * K : 0);
         }
         x.dpk = bytes;
         bytes += align256(sizeof(T) * (size_t)x.dbase[kMaxGroups]);
+        if (tri) {
+            x.tmp = bytes;
+            bytes += align256(sizeof(double) * (size_t)x.tbase[kMaxGroups]);
+        }
     } else {
         long long tot = 0;
         for (int l = 0; l < pl->nlevels; ++l) {
@@ -213,10 +223,20 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                 if (grid_op(t.op)) {
                     const bool tau = t.op == GPW_OP_TAU;
                     T *Dpk = (T *)(scr + ts[i].dpk) + ts[i].dbase[g];
-                    const long long ne = (tau || rho_tensor(cls_la(c), cls_lb(c)))
-                                             ? np
-                                             : np * ncart(cls_la(c)) * ncart(cls_lb(c));
-                    (tau ? cl.tpacks : cl.packs).add({0, pairs, t.D, Dpk, ne, pl->n_ao}, nb256(ne));
+                    if (pl->tri) {
+                        // Cartesian tensors in FP64, then on the index offset
+                        double *tmp = (double *)(scr + ts[i].tmp) + ts[i].tbase[g];
+                        const int Lt = cls_la(c) + cls_lb(c) + extra_degree(t.op), K = ntab(Lt);
+                        (tau ? cl.tpacks : cl.packs_t)
+                            .add({0, pairs, t.D, Dpk, np, pl->n_ao, pl->geom[l].tri, tmp}, nb256(np));
+                        cl.idxs.add({0, tmp, Dpk, np * K, Lt, K, cstride<T>(K), pl->geom[l].tri}, nb256(np * K));
+                    } else {
+                        const long long ne = (tau || rho_tensor(cls_la(c), cls_lb(c)))
+                                                 ? np
+                                                 : np * ncart(cls_la(c)) * ncart(cls_lb(c));
+                        (tau ? cl.tpacks : cl.packs).add({0, pairs, t.D, Dpk, ne, pl->n_ao, nullptr, nullptr},
+                                                         nb256(ne));
+                    }
                     RhoSeg r;
                     r.item0 = 0;
                     r.count = pl->blk_off[g + 1] - pl->blk_off[g];
@@ -228,7 +248,10 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                     r.rho = t.rho[l];
                     r.p0 = (int)pl->group_off[g];
                     r.G = pl->geom[l];
-                    (tau ? cl.taus : cl.rhos).add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
+                    if (pl->tri)
+                        (tau ? cl.taus_t : cl.rhos_t).add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
+                    else
+                        (tau ? cl.taus : cl.rhos).add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
                 } else {
                     PairSeg q;
                     q.item0 = 0;
@@ -241,15 +264,23 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                     q.emax = emax;
                     q.vz = block_column(pl, l);
                     q.G = pl->geom[l];
-                    (t.op == GPW_OP_MAT       ? cl.mats
-                     : t.op == GPW_OP_GRAD    ? cl.grads
-                     : t.op == GPW_OP_MAT_TAU ? cl.mtaus
-                                              : cl.gtaus)
-                        .add(q, np);
+                    if (pl->tri)
+                        (t.op == GPW_OP_MAT       ? cl.mats_t
+                         : t.op == GPW_OP_GRAD    ? cl.grads_t
+                         : t.op == GPW_OP_MAT_TAU ? cl.mtaus_t
+                                                  : cl.gtaus_t)
+                            .add(q, np);
+                    else
+                        (t.op == GPW_OP_MAT       ? cl.mats
+                         : t.op == GPW_OP_GRAD    ? cl.grads
+                         : t.op == GPW_OP_MAT_TAU ? cl.mtaus
+                                                  : cl.gtaus)
+                            .add(q, np);
                 }
             }
         }
         cl.smem = PairSmem<T>::bytes(emax_all);
+        cl.smem_t = PairSmem<T>::bytes(emax_all, true);
         cl.st = st;
         cl.fp32 = std::is_same<T, float>::value;
         launch_class(c, cl);
@@ -285,9 +316,9 @@ void launch_class(int c, const ClassLaunch &cl)
     fn[c](cl);
 }
 
-size_t pair_kernel_lds_bytes(int emax, int precision)
+size_t pair_kernel_lds_bytes(int emax, int precision, bool tri)
 {
-    return precision == GPW_FP32 ? PairSmem<float>::bytes(emax) : PairSmem<double>::bytes(emax);
+    return precision == GPW_FP32 ? PairSmem<float>::bytes(emax, tri) : PairSmem<double>::bytes(emax, tri);
 }
 
 // ------------------------------------------------- evaluation without allocation

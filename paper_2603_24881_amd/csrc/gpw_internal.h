@@ -93,12 +93,37 @@ struct alignas(128) RhoRec {
 };
 static_assert(sizeof(RhoRec) == 128, "RhoRec layout");
 
+// Highest degree of the monomial transforms of a general cell (the moments of
+// the meta-GGA gradient of a (g|g) pair).
+constexpr int kMaxTDeg = 11;
+
+// Geometry of one level of a general (non-orthogonal) cell, in device memory.
+// Grid point i sits at r = sum_d i_d h_d with the step vectors h_d = a_d / N_d;
+// the kernels then work in grid-index coordinates s (r = s H, H the rows h_d):
+// positions, products and offsets in index units, the envelope
+// exp(-alpha |r - P|^2) = exp(-alpha (s - s_P)^T g (s - s_P)) with the metric
+// g = H H^T, whose off-diagonal terms give the cross factors of the
+// non-orthogonal recursion.  Cartesian monomials of r - A and monomials of
+// the index offset s - s_A of the same degree n are related by T_n:
+// (r - A)^m = sum_k T_n[m][k] (s - s_A)^k (m, k Cartesian exponents in shell
+// order).
+struct TriGeom {
+    double H[3][3];        // step vectors as rows (bohr)
+    double Hinv[3][3];     // s = r Hinv
+    double g[3][3];        // metric h_d . h_e
+    double lmin;           // smallest eigenvalue of g: |r|^2 >= lmin |s|^2
+    double rf[3];          // |Hinv[:, d]|: index-box half width per unit radius
+    int toff[kMaxTDeg + 1];   // offset of T_n in T
+    const double *T;       // T_n, n = 0..kMaxTDeg, row-major ncart(n) x ncart(n)
+};
+
 // Per-level geometry passed by value to kernels.
 struct LevelGeom {
     int N[3];         // mesh
     int nb[3];        // 4^3 blocks per axis (ceil(N/4))
-    double h[3];      // grid spacing
+    double h[3];      // grid spacing (index units, 1, for a general cell)
     double w;         // quadrature weight Omega / N_l
+    const TriGeom *tri;   // general cell: device geometry of the level; nullptr: orthorhombic
 };
 
 // Slot of a 4x4x4 block in the per-group incidence lists: tiles of 8x8x8
@@ -250,7 +275,10 @@ struct PsTable {
 };
 
 struct PlanConst {
-    double L[3];
+    double L[3];          // |a_d|
+    int tri;              // general cell
+    double A[3][3];       // lattice vectors as rows
+    double Ainv[3][3];    // r = u A, u = r Ainv (fractional coordinates)
     double logtau;
     double rel_cut;
     int nlevels;
@@ -270,7 +298,13 @@ struct PoissonState;   // FFT plans of the multigrid transfer (gpw_poisson.hip)
 struct gpw_plan_s {
     int device = 0;
     int precision = GPW_FP64;
-    double L[3] = {0, 0, 0};
+    double L[3] = {0, 0, 0};          // |a_d|
+    int tri = 0;                      // general (non-orthogonal) cell
+    double A[3][3] = {};              // lattice vectors as rows
+    double recip[3][3] = {};          // reciprocal vectors b_d = 2 pi (A^-1)[:, d] as rows
+    double volume = 0.0;
+    gpw::TriGeom tri_host[gpw::kMaxLevels] = {};   // host copies (device pointers inside)
+    gpw::TriGeom *d_tri = nullptr;                 // per level, device
     int nlevels = 0;
     gpw::LevelGeom geom[gpw::kMaxLevels];
     long long ngrid[gpw::kMaxLevels] = {};
@@ -339,5 +373,5 @@ void poisson_free(gpw_plan_s *pl);
 size_t poisson_spectra_bytes(const gpw_plan_s *pl);
 // LDS bytes a workgroup of the pair-major kernels (mat, grad) needs for a plan
 // whose longest per-axis block list of a pair image has emax entries.
-size_t pair_kernel_lds_bytes(int emax, int precision);
+size_t pair_kernel_lds_bytes(int emax, int precision, bool tri);
 }  // namespace gpw

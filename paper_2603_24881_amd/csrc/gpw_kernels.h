@@ -70,7 +70,15 @@ __device__ __forceinline__ int seg_of(const SegTable<S> &t, long long item)
 struct FillSeg { long long item0; double *p; long long count; };
 struct GridSeg { long long item0; const double *v; double *vb; long long count; int vz; LevelGeom G; };
 struct SymSeg { long long item0; const double *D; void *out; int n, nt; };
-struct PackSeg { long long item0; const PairRec *pairs; const double *D; void *out; long long count; int n; };
+// tri (a general cell): the coefficients are formed on the Cartesian
+// monomials and written in FP64 to tmp, for k_to_index
+struct PackSeg {
+    long long item0; const PairRec *pairs; const double *D; void *out; long long count; int n;
+    const TriGeom *tri; double *tmp;
+};
+// Cartesian coefficient tensors of degree L (K = ntab(L) per pair image, in
+// src) rewritten on the monomials of the index offset into dst (stride cs)
+struct IdxSeg { long long item0; const double *src; void *dst; long long count; int L, K, cs; const TriGeom *tri; };
 // one wave per grid block (rho) or per pair image (mat, grad)
 // Their workgroup ranges are padded to multiples of 8 and mapped to items
 // with xcd_item inside the segment, so that every segment (a level of a
@@ -244,6 +252,68 @@ __device__ __forceinline__ void block_envelope(double alpha, const double *d, co
     }
 }
 
+// General cell (index coordinates s, metric g; the non-orthogonal recursion
+// of the appendix applied block-wise): with d = s0 - s_P at the block's first
+// point and t the offset in the block,
+//   exp(-alpha (d + t)^T g (d + t)) = fx[tx] fy[ty] fz[tz] Qxy^(tx ty) Qxz^(tx tz) Qyz^(ty tz),
+// fx[0] = exp(-alpha d^T g d), fy[0] = fz[0] = 1, per axis the recursion
+// f_{t+1} = f_t exp(-2 alpha (g d)_k) c_k^(2t+1) with c_k = exp(-alpha g_kk),
+// and the cross factors Q_de = exp(-2 alpha g_de).  Single factors can be
+// large where the Gaussian is sharp on the level's grid far from the block;
+// when one could leave the FP64 range the lane takes one exp per point
+// instead (direct).
+struct TriEnv {
+    double q[3];     // Qxy, Qxz, Qyz
+    double ap, qd;   // alpha_p and d^T g d (direct form)
+    double gd[3];    // g d (direct form)
+    bool direct;
+};
+__device__ __forceinline__ void block_envelope_tri(double alpha, const double *d, const TriGeom *tg, const double *c,
+                                                   double *fx, double *fy, double *fz, TriEnv &te)
+{
+    double *f[3] = {fx, fy, fz};
+    const double(*g)[3] = tg->g;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) te.gd[k] = g[k][0] * d[0] + g[k][1] * d[1] + g[k][2] * d[2];
+    te.qd = d[0] * te.gd[0] + d[1] * te.gd[1] + d[2] * te.gd[2];
+    te.ap = alpha;
+    // largest exponent a factor or partial product reaches
+    double big = alpha * te.qd;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double off = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j != k) off += fabs(g[k][j]);
+        big = fmax(big, alpha * (6.0 * fabs(te.gd[k]) + 9.0 * g[k][k] + 18.0 * off));
+    }
+    te.direct = big > 600.0;
+    te.q[0] = exp(-2.0 * alpha * g[0][1]);
+    te.q[1] = exp(-2.0 * alpha * g[0][2]);
+    te.q[2] = exp(-2.0 * alpha * g[1][2]);
+    f[0][0] = te.direct ? 0.0 : exp(-alpha * te.qd);
+    f[1][0] = 1.0;
+    f[2][0] = 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double c2 = c[k] * c[k];
+        double r = te.direct ? 0.0 : exp(-2.0 * alpha * te.gd[k]) * c[k];
+        f[k][1] = f[k][0] * r;
+        r *= c2;
+        f[k][2] = f[k][1] * r;
+        r *= c2;
+        f[k][3] = f[k][2] * r;
+    }
+}
+
+// q^n for n = 0..3
+template <typename T>
+__device__ __forceinline__ T pow03(T q, int n)
+{
+    const T q2 = q * q;
+    return n == 0 ? T(1) : n == 1 ? q : n == 2 ? q2 : q2 * q;
+}
+
 // Transpose-reduction through LDS: lane l holds acc[j], its pair images'
 // partial density at point p0 + j (j < NP); afterwards the lane that owns
 // point p0 + j (lane index = point index) holds the sum over all lanes.
@@ -265,6 +335,19 @@ __device__ __forceinline__ void reduce_points(const T *acc, double (*red)[65], i
         for (int o = CH; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
         if (lane == p0 + c0 + j) out = s;
         __syncthreads();
+    }
+}
+
+// A - B' of a pair image in Cartesian units: a general cell's records hold it
+// in index units (s = r Hinv), so r = s H.
+__device__ __forceinline__ void cart_ab(const PairRec &r, const TriGeom *tg, double *AB)
+{
+    if (tg) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) AB[c] = r.AB[0] * tg->H[0][c] + r.AB[1] * tg->H[1][c] + r.AB[2] * tg->H[2][c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) AB[c] = r.AB[c];
     }
 }
 
@@ -340,21 +423,29 @@ k_pack_density(SegTable<PackSeg> tab)
     const PackSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long lp = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
     if (lp >= sg.count) return;
-    T *__restrict__ out = (T *)sg.out + lp * cstride<T>(K);
     const PairRec &r = sg.pairs[lp];
+    double AB[3];
+    cart_ab(r, sg.tri, AB);
     double ab[3][LB + 1];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         ab[d][0] = 1.0;
 #pragma unroll
-        for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * r.AB[d];
+        for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * AB[d];
     }
     double C[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) C[k] = 0.0;
     pack_terms<LA, LB>(std::make_integer_sequence<int, NA * NB>{}, C, sg.D, sg.n, r.ao_a, r.ao_b, 0.5 * r.Kw, ab);
+    if (sg.tri) {
+        double *__restrict__ o = sg.tmp + lp * K;
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = (T)C[k];
+        for (int k = 0; k < K; ++k) o[k] = C[k];
+    } else {
+        T *__restrict__ out = (T *)sg.out + lp * cstride<T>(K);
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = (T)C[k];
+    }
 }
 
 // ------------------------------------------------- kinetic energy density terms
@@ -429,14 +520,15 @@ k_pack_tau(SegTable<PackSeg> tab)
     const PackSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long lp = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
     if (lp >= sg.count) return;
-    T *__restrict__ out = (T *)sg.out + lp * cstride<T>(K);
     const PairRec &r = sg.pairs[lp];
+    double AB[3];
+    cart_ab(r, sg.tri, AB);
     double ab[3][LB + 2];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         ab[d][0] = 1.0;
 #pragma unroll
-        for (int k = 1; k <= LB + 1; ++k) ab[d][k] = ab[d][k - 1] * r.AB[d];
+        for (int k = 1; k <= LB + 1; ++k) ab[d][k] = ab[d][k - 1] * AB[d];
     }
     double C[K];
 #pragma unroll
@@ -444,8 +536,55 @@ k_pack_tau(SegTable<PackSeg> tab)
     // 1/2 of tau times the 1/2 of the symmetrisation
     tau_terms<LA, LB>(std::make_integer_sequence<int, NA * NB>{}, C, sg.D, sg.n, r.ao_a, r.ao_b, 0.25 * r.Kw,
                       2.0 * r.aa, 2.0 * r.ab, ab);
+    if (sg.tri) {
+        double *__restrict__ o = sg.tmp + lp * K;
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = (T)C[k];
+        for (int k = 0; k < K; ++k) o[k] = C[k];
+    } else {
+        T *__restrict__ out = (T *)sg.out + lp * cstride<T>(K);
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = (T)C[k];
+    }
+}
+
+// (lx, ly, lz) of entry k of the lx-major tensor layout of degree <= L
+// (inverse of tidx)
+__device__ __forceinline__ void tidx_decode(int L, int k, int &lx, int &ly, int &lz)
+{
+    lx = 0;
+    while (k >= ntab2(L - lx)) {
+        k -= ntab2(L - lx);
+        ++lx;
+    }
+    ly = t2_ly(L - lx, k);
+    lz = t2_lz(L - lx, k);
+}
+
+// A general cell's coefficient tensors on the monomials of the index offset:
+// with (r - A)^m = sum_k T_n[m][k] (s - s_A)^k over the monomials of one
+// degree n, a polynomial sum_m C_m (r - A)^m has the coefficients
+// C'_k = sum_m C_m T_n[m][k].  One thread per (pair image, coefficient).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_to_index(SegTable<IdxSeg> tab)
+{
+    const IdxSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
+    const long long e = (long long)(blockIdx.x - sg.item0) * 256 + threadIdx.x;
+    if (e >= sg.count) return;
+    const int K = sg.K, L = sg.L;
+    const long long lp = e / K;
+    const int k = (int)(e - lp * K);
+    int kx, ky, kz;
+    tidx_decode(L, k, kx, ky, kz);
+    const int n = kx + ky + kz, nc = ncart(n), ks = cart_index(ky, kz);
+    const double *__restrict__ Tn = sg.tri->T + sg.tri->toff[n];
+    const double *__restrict__ src = sg.src + lp * K;
+    double v = 0.0;
+    for (int m = 0; m < nc; ++m) {
+        const int mx = cart_lx(n, m), my = cart_ly(n, m);
+        v += src[tidx(L, mx, my, n - mx - my)] * Tn[m * nc + ks];
+    }
+    ((T *)sg.dst)[lp * sg.cs + k] = (T)v;
 }
 
 // Per-lane state of one pair image in the rho kernel.  The record and the D
@@ -570,10 +709,16 @@ __device__ __forceinline__ void horner_y_all(const T *cyz, T ya, T *cz, std::int
 // the envelope E = fx fy fz cut at ER.  The polynomial is evaluated by
 // Horner's rule one axis at a time: per x point its coefficients in (y, z),
 // per (x, y) column those in z, per point the z polynomial (Eq. (rho1)).
-template <int L, int NX, typename T>
+// TRI (a general cell): coordinates and monomials in index units, and the
+// cross factors of block_envelope_tri enter the envelope,
+// E = fx[tx] fy[ty] Qxy^(tx ty) fz[tz] (Qxz^tx Qyz^ty)^tz, formed in FP64
+// (single factors may exceed the float range; the partial products from fx
+// on are envelope values, at most 1), or per point from d^T g d, g d and g
+// for a lane in the direct form.
+template <int L, int NX, typename T, bool TRI = false>
 __device__ __forceinline__ void rho_points(const T *Ct, double xa0, double ya0, double za0, const LevelGeom &G,
                                            const double *fx, const double *fy, const double *fz, T ER, T on,
-                                           int tx0, T *acc)
+                                           int tx0, T *acc, const TriEnv *te = nullptr)
 {
     T zat[4], fzt[4];   // z offsets and factors, the same for every column
 #pragma unroll
@@ -587,19 +732,44 @@ __device__ __forceinline__ void rho_points(const T *Ct, double xa0, double ya0, 
         const T ex = (T)fx[ix] * on;
         T cyz[ntab2(L)];
         horner_x_all<L, T>(Ct, xa, cyz, std::make_integer_sequence<int, ntab2(L)>{});
+        double qxy = 1.0, qxz = 1.0;   // Qxy^tx, Qxz^tx
+        if constexpr (TRI) {
+            qxy = pow03<double>(te->q[0], tx0 + ix);
+            qxz = pow03<double>(te->q[1], tx0 + ix);
+        }
 #pragma unroll
         for (int ty = 0; ty < 4; ++ty) {
             const T ya = (T)(ya0 + ty * G.h[1]);
-            const T exy = ex * (T)fy[ty];
             T cz[L + 1];
             horner_y_all<L, T>(cyz, ya, cz, std::make_integer_sequence<int, L + 1>{});
             // the four points of the column side by side: independent chains
             T E[4], q[4];
+            if constexpr (TRI) {
+                if (!te->direct) {
+                    const double exy = fx[ix] * fy[ty] * pow03<double>(qxy, ty);
+                    const double m = qxz * pow03<double>(te->q[2], ty), m2 = m * m;
+                    E[0] = (T)(exy * fz[0]) * on;
+                    E[1] = (T)(exy * (fz[1] * m)) * on;
+                    E[2] = (T)(exy * (fz[2] * m2)) * on;
+                    E[3] = (T)(exy * (fz[3] * (m2 * m))) * on;
+                } else {
+                    // (d + t)^T g (d + t) = d^T g d + 2 t . g d + t^T g t
+                    const double(*g)[3] = G.tri->g;
+                    const double tx = tx0 + ix, tyd = ty;
+                    const double qxy2 = te->qd + 2.0 * (tx * te->gd[0] + tyd * te->gd[1]) + g[0][0] * tx * tx +
+                                        g[1][1] * tyd * tyd + 2.0 * g[0][1] * tx * tyd;
+                    const double lz = 2.0 * (te->gd[2] + g[0][2] * tx + g[1][2] * tyd);
 #pragma unroll
-            for (int tz = 0; tz < 4; ++tz) {
-                E[tz] = exy * fzt[tz];
-                q[tz] = cz[L];
+                    for (int tz = 0; tz < 4; ++tz)
+                        E[tz] = (T)exp(-te->ap * (qxy2 + tz * (lz + g[2][2] * tz))) * on;
+                }
+            } else {
+                const T exy = ex * (T)fy[ty];
+#pragma unroll
+                for (int tz = 0; tz < 4; ++tz) E[tz] = exy * fzt[tz];
             }
+#pragma unroll
+            for (int tz = 0; tz < 4; ++tz) q[tz] = cz[L];
 #pragma unroll
             for (int lz = L - 1; lz >= 0; --lz)
 #pragma unroll
@@ -658,22 +828,24 @@ __device__ __forceinline__ void rho_points_direct(const T *Dk, double xa0, doubl
 
 // One lane's contributions, in the form the class uses.  XL = 2: the
 // kinetic energy density, always through its coefficient tensor of degree
-// l_a + l_b + 2.
-template <int LA, int LB, int XL, int NX, typename T>
+// l_a + l_b + 2.  A general cell (TRI) always takes the tensor form, whose
+// monomials are those of the index offset.
+template <int LA, int LB, int XL, int NX, typename T, bool TRI = false>
 __device__ __forceinline__ void rho_lane_points(const T *C, double xa0, double ya0, double za0, const double *AB,
                                                 const LevelGeom &G, const double *fx, const double *fy,
-                                                const double *fz, T ER, T on, int tx0, T *acc)
+                                                const double *fz, T ER, T on, int tx0, T *acc,
+                                                const TriEnv *te = nullptr)
 {
-    if constexpr (XL > 0 || rho_tensor(LA, LB))
-        rho_points<LA + LB + XL, NX, T>(C, xa0, ya0, za0, G, fx, fy, fz, ER, on, tx0, acc);
+    if constexpr (TRI || XL > 0 || rho_tensor(LA, LB))
+        rho_points<LA + LB + XL, NX, T, TRI>(C, xa0, ya0, za0, G, fx, fy, fz, ER, on, tx0, acc, te);
     else
         rho_points_direct<LA, LB, NX, T>(C, xa0, ya0, za0, AB, G, fx, fy, fz, ER, on, tx0, acc);
 }
 
 // Coefficients per pair image in the packed rho / tau inputs.
-__host__ __device__ constexpr int grid_ncoef(int la, int lb, int xl)
+__host__ __device__ constexpr int grid_ncoef(int la, int lb, int xl, bool tri = false)
 {
-    return xl > 0 ? ntab(la + lb + xl) : rho_ncoef(la, lb);
+    return (xl > 0 || tri) ? ntab(la + lb + xl) : rho_ncoef(la, lb);
 }
 
 // Density of one (level, class) group on its nonempty 4x4x4 blocks.  One wave
@@ -686,12 +858,12 @@ __host__ __device__ constexpr int grid_ncoef(int la, int lb, int xl)
 // before the current batch is computed, so their latency hides behind the
 // arithmetic.  NPASS splits the 64 points to bound the accumulator registers.
 // XL = 0: density; XL = 2: kinetic energy density (its coefficient tensor).
-template <int LA, int LB, int XL, int NPASS, bool STG, bool PREF, typename T>
+template <int LA, int LB, int XL, int NPASS, bool STG, bool PREF, typename T, bool TRI = false>
 __device__ __forceinline__ void rho_blocks(const SegTable<RhoSeg> &tab)
 {
     constexpr int NX = 4 / NPASS;
     constexpr int NP = 16 * NX;
-    using Lane = RhoLane<T, grid_ncoef(LA, LB, XL)>;
+    using Lane = RhoLane<T, grid_ncoef(LA, LB, XL, TRI)>;
     constexpr int LDSB = STG && Lane::STAGE > 32 * 65 * 8 ? Lane::STAGE : 32 * 65 * 8;
     // the batch staging area, and after the last batch the reduction buffer
     __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
@@ -753,7 +925,11 @@ __device__ __forceinline__ void rho_blocks(const SegTable<RhoSeg> &tab)
             const double y0 = (double)(4 * kk[1] + shift_of(en.y, 1) * G.N[1]) * G.h[1];
             const double z0 = (double)(4 * kk[2] + shift_of(en.y, 2) * G.N[2]) * G.h[2];
             const double dP[3] = {x0 - cur.P[0], y0 - cur.P[1], z0 - cur.P[2]};
-            block_envelope(cur.ap, dP, G, cur.c, fx, fy, fz);
+            TriEnv te;
+            if constexpr (TRI)
+                block_envelope_tri(cur.ap, dP, G.tri, cur.c, fx, fy, fz, te);
+            else
+                block_envelope(cur.ap, dP, G, cur.c, fx, fy, fz);
             const T ER = (T)cur.ER;
             const T on = act ? T(1) : T(0);
             const double xa0 = x0 - cur.A[0], ya0 = y0 - cur.A[1], za0 = z0 - cur.A[2];
@@ -765,8 +941,8 @@ __device__ __forceinline__ void rho_blocks(const SegTable<RhoSeg> &tab)
                 for (int q = 1; q < NPASS; ++q)
                     if (pass == q) fxp[ix] = fx[q * NX + ix];
             }
-            rho_lane_points<LA, LB, XL, NX, T>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on, pass * NX,
-                                               acc);
+            rho_lane_points<LA, LB, XL, NX, T, TRI>(cur.Ct, xa0, ya0, za0, cur.AB, G, fxp, fy, fz, ER, on,
+                                                    pass * NX, acc, &te);
         }
         reduce_points<NP, T>(acc, red, pass * NP, mine);
     }
@@ -783,6 +959,23 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WP
 k_rho(SegTable<RhoSeg> tab)
 {
     rho_blocks<LA, LB, 0, NPASS, STG, PREF, T>(tab);
+}
+
+// The density and the kinetic energy density of a general cell: index
+// coordinates, the cross factors of block_envelope_tri, coefficients in the
+// monomials of the index offset (k_to_index).  No staging; NPASS bounds the
+// accumulators next to the cross factors.
+template <int LA, int LB, int NPASS, typename T>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_rho_tri(SegTable<RhoSeg> tab)
+{
+    rho_blocks<LA, LB, 0, NPASS, false, false, T, true>(tab);
+}
+template <int LA, int LB, int NPASS, typename T>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_tau_tri(SegTable<RhoSeg> tab)
+{
+    rho_blocks<LA, LB, 2, NPASS, false, false, T, true>(tab);
 }
 
 // Kinetic energy density tau(r) = 1/2 sum D grad a . grad b (Sec. II, the
@@ -969,11 +1162,17 @@ template <typename T> struct alignas(4 * sizeof(T)) PtZ { T e, a, b, c; };
 // shifts) its bounding box meets, one entry per lane, and the point tables of
 // the entries, so that the points of a run of consecutive entries sit at
 // consecutive table positions.  emax bounds every list (the plan's longest).
-template <bool MOM, typename T>
+// TRI (a general cell, index units): the tables hold the offset from P in
+// place of the envelope factor (the envelope does not separate; the visitor
+// forms it per point), and the gaps are scaled by the metric's smallest
+// eigenvalue so that their sum stays below the squared distance.
+template <bool MOM, typename T, bool TRI = false>
 __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G, PtXY<T> *txy, PtZ<T> *tz,
                                            AxisBlock *bl, int emax, int *cnt)
 {
     const double ap = r.aa + r.ab;
+    double gs = 1.0;
+    if constexpr (TRI) gs = G.tri->lmin;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int N = G.N[d], nb = G.nb[d];
@@ -990,7 +1189,7 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             AxisBlock eb;
             eb.k = k;
             eb.pad = 0;
-            eb.gap2 = axis_gap2(r.P[d], (double)u0 * G.h[d], (double)u1 * G.h[d]);
+            eb.gap2 = gs * axis_gap2(r.P[d], (double)u0 * G.h[d], (double)u1 * G.h[d]);
             bl[d * emax + e] = eb;
         }
         // points of the entries; a partial block's padding points get the
@@ -1004,7 +1203,7 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             const int u = 4 * k + (i & 3) + S * N;
             const double x = (double)u * G.h[d];
             const double dx = x - r.P[d];
-            const double e = exp(-ap * dx * dx), a = x - r.A[d];
+            const double e = TRI ? dx : exp(-ap * dx * dx), a = x - r.A[d];
             if (d < 2) {
                 txy[d * 4 * emax + i] = PtXY<T>{(T)e, (T)a};
             } else {
@@ -1207,6 +1406,7 @@ struct TensorVisit {
     T ER;
     T xa = 0, ex = 0, ya = 0, ey = 0, exy = 0;
     int xcur = -1;
+    __device__ TensorVisit(const PairRec &r, const LevelGeom &) : TensorVisit(r) {}
     __device__ explicit TensorVisit(const PairRec &r) : ER((T)r.ER)
     {
 #pragma unroll
@@ -1282,6 +1482,126 @@ struct TensorVisit {
     }
 };
 
+template <typename T> __device__ __forceinline__ T texp(T x);
+template <> __device__ __forceinline__ double texp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float texp<float>(float x) { return expf(x); }
+
+// The moments of a general cell (index units): sum_r v(r) E(r) (s - s_A)^k
+// over the monomials of the index offset, with the envelope
+// E = exp(-alpha_p q), q = (s - s_P)^T g (s - s_P) = |r - P|^2, formed per point
+// from the row's part (x and y offsets) and the z offset in the table, and
+// the point kept iff q <= R^2.  Accumulated one axis at a time as in
+// TensorVisit, with the envelope applied per point.
+template <int L, typename T>
+struct TensorVisitTri {
+    static constexpr int K = ntab(L), K2 = ntab2(L);
+    T Vm[K], U[K2], W[L + 1];
+    T R2, nap;
+    T gxx, gyy, gzz, gxy2, gxz2, gyz2;   // metric, off-diagonal terms doubled
+    T xa = 0, ya = 0, qrow = 0, crow = 0;
+    int xcur = -1;
+    __device__ TensorVisitTri(const PairRec &r, const LevelGeom &G) : R2((T)r.R2), nap((T)(-(r.aa + r.ab)))
+    {
+        const double(*g)[3] = G.tri->g;
+        gxx = (T)g[0][0];
+        gyy = (T)g[1][1];
+        gzz = (T)g[2][2];
+        gxy2 = (T)(2.0 * g[0][1]);
+        gxz2 = (T)(2.0 * g[0][2]);
+        gyz2 = (T)(2.0 * g[1][2]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) Vm[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < K2; ++k) U[k] = T(0);
+#pragma unroll
+        for (int k = 0; k <= L; ++k) W[k] = T(0);
+    }
+    __device__ __forceinline__ void flush_row()
+    {
+        T g = T(1);
+#pragma unroll
+        for (int ly = 0; ly <= L; ++ly) {
+#pragma unroll
+            for (int lz = 0; ly + lz <= L; ++lz) U[t2idx(L, ly, lz)] += W[lz] * g;
+            g *= ya;
+        }
+#pragma unroll
+        for (int k = 0; k <= L; ++k) W[k] = T(0);
+    }
+    __device__ __forceinline__ void flush_x()
+    {
+        T g = T(1);
+#pragma unroll
+        for (int lx = 0; lx <= L; ++lx) {
+#pragma unroll
+            for (int ly = 0; lx + ly <= L; ++ly)
+#pragma unroll
+                for (int lz = 0; lx + ly + lz <= L; ++lz) Vm[tidx(L, lx, ly, lz)] += U[t2idx(L, ly, lz)] * g;
+            g *= xa;
+        }
+#pragma unroll
+        for (int k = 0; k < K2; ++k) U[k] = T(0);
+    }
+    // X.e, Y.e: offsets from P; X.a, Y.a: offsets from A
+    __device__ __forceinline__ void row(int exn, const PtXY<T> &X, const PtXY<T> &Y)
+    {
+        if (xcur >= 0) {
+            flush_row();
+            if (exn != xcur) flush_x();
+        }
+        xcur = exn;
+        xa = X.a;
+        ya = Y.a;
+        const T dx = X.e, dy = Y.e;
+        qrow = gxx * dx * dx + gxy2 * dx * dy + gyy * dy * dy;
+        crow = gxz2 * dx + gyz2 * dy;
+    }
+    // Z.e: z offset from P; Z.a, Z.b, Z.c: (z - A_z), its square and cube
+    __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
+    {
+        const T q = qrow + Z.e * (gzz * Z.e + crow);
+        const T f = (q <= R2) ? v * texp<T>(nap * q) : T(0);
+        W[0] += f;
+        if constexpr (L >= 1) W[1] += f * Z.a;
+        if constexpr (L >= 2) W[2] += f * Z.b;
+        if constexpr (L >= 3) W[3] += f * Z.c;
+        if constexpr (L >= 4) {
+            T p = Z.c;
+#pragma unroll
+            for (int lz = 4; lz <= L; ++lz) {
+                p *= Z.a;
+                W[lz] += f * p;
+            }
+        }
+    }
+    __device__ __forceinline__ void done()
+    {
+        if (xcur >= 0) {
+            flush_row();
+            flush_x();
+        }
+    }
+};
+
+// Cartesian moments of a general cell's pair image from those of the index
+// offset (degree <= L, tensor layout): with (r - A)^m = sum_k T_n[m][k]
+// (s - s_A)^k, M_m = sum_k T_n[m][k] M'_k.  The wave splits the entries.
+__device__ __forceinline__ void moments_to_cart(int L, const TriGeom *tg, const double *ms, double *mc)
+{
+    for (int e = threadIdx.x; e < ntab(L); e += 64) {
+        int mx, my, mz;
+        tidx_decode(L, e, mx, my, mz);
+        const int n = mx + my + mz, nc = ncart(n);
+        const double *__restrict__ Tn = tg->T + tg->toff[n] + cart_index(my, mz) * nc;
+        double v = 0.0;
+        for (int k = 0; k < nc; ++k) {
+            const int kx = cart_lx(n, k), ky = cart_ly(n, k);
+            v += Tn[k] * ms[tidx(L, kx, ky, n - kx - ky)];
+        }
+        mc[e] = v;
+    }
+}
+
 // Wave sums of the K per-lane accumulators of a pair-major kernel, eight at
 // a time through LDS (red[8][65], the kernel's LDS area once the traversal is
 // done): lane 8q + s adds eight values of accumulator q, three shuffles
@@ -1289,6 +1609,8 @@ struct TensorVisit {
 // eight results of a chunk leave in parallel instead of one lane issuing
 // every atomic.
 constexpr size_t kRedBytes = (8 * 65 + 364) * sizeof(double);   // red[8][65] and up to ntab(11) moments
+// a general cell: both sets of moments (index offset and Cartesian)
+constexpr size_t kRedBytesTri = (8 * 65 + 2 * 364) * sizeof(double);
 template <int K, typename T, typename Emit>
 __device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit &&emit)
 {
@@ -1330,13 +1652,50 @@ struct PairSmem {
         cnt = reinterpret_cast<int *>(bl + 3 * emax);
         rows = reinterpret_cast<BlockRow *>(cnt + 4);
     }
-    static size_t bytes(int emax)
+    static size_t bytes(int emax, bool tri = false)
     {
         const size_t off = table_bytes(emax);
         const size_t b = off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)emax * emax;
-        return b > kRedBytes ? b : kRedBytes;   // the area is reused for the final reduction
+        const size_t red = tri ? kRedBytesTri : kRedBytes;
+        return b > red ? b : red;   // the area is reused for the final reduction
     }
 };
+
+// Moments of degree LT of one pair image (pair-major traversal), wave-summed
+// into LDS past the reduction area; returns their address.  A general cell
+// (TRI) accumulates the moments of the index offset and returns the
+// Cartesian moments formed from them (after the first set).
+template <int LT, typename T, bool TRI = false>
+__device__ __forceinline__ const double *pair_moments(const PairSeg &sg, const PairRec &r, unsigned char *smem_raw)
+{
+    PtXY<T> *txy;
+    PtZ<T> *tz;
+    AxisBlock *bl;
+    int *cnt;
+    BlockRow *rows;
+    const LevelGeom &G = sg.G;
+    const int emax = sg.emax;
+    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
+    pair_setup<true, T, TRI>(r, G, txy, tz, bl, emax, cnt);
+    __syncthreads();
+    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
+    __syncthreads();
+    using Vis = std::conditional_t<TRI, TensorVisitTri<LT, T>, TensorVisit<LT, T>>;
+    Vis vis(r, G);
+    for_each_point<T>(txy, tz, emax, rows, nrows, sg.Vb, vis);
+    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+    double *red = reinterpret_cast<double *>(smem_raw);
+    double *mom = red + 8 * 65;
+    wave_reduce_emit<ntab(LT), T>(vis.Vm, red, [&](int k, double v) { mom[k] = v; });
+    __syncthreads();
+    if constexpr (TRI) {
+        double *mc = mom + ntab(LT);
+        moments_to_cart(LT, G.tri, mom, mc);
+        __syncthreads();
+        return mc;
+    }
+    return mom;
+}
 
 // Matrix element (I, J) of a pair image from its potential moments:
 // sum over the binomial expansion of (x-B)^b around A (Eq. (binomial)) of
@@ -1369,31 +1728,33 @@ __device__ __forceinline__ void mat_elements(std::integer_sequence<int, E...>, c
     ((lane == E % 64 ? (void)(m[E / 64] = mat_element<LA, LB, E / NB, E % NB>(mom, ab)) : (void)0), ...);
 }
 
-template <int LA, int LB, typename T>
+// TRI: a general cell, always through the moments (formed on the index
+// offset, then made Cartesian).
+template <int LA, int LB, typename T, bool TRI = false>
 __global__ void __launch_bounds__(64)
 k_mat(SegTable<PairSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
-    PtXY<T> *txy;
-    PtZ<T> *tz;
-    AxisBlock *bl;
-    int *cnt;
-    BlockRow *rows;
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const LevelGeom &G = sg.G;
-    const int n_ao = sg.n_ao, emax = sg.emax;
-    const double *__restrict__ Vb = sg.Vb;
-    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
+    const int n_ao = sg.n_ao;
     const PairRec &r = sg.pairs[item];
-    pair_setup<mat_tensor(LA, LB), T>(r, G, txy, tz, bl, emax, cnt);
-    __syncthreads();
-    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
-    __syncthreads();
     const double scale = 0.5 * G.w * r.Kw;
-    if constexpr (!mat_tensor(LA, LB)) {
+    if constexpr (!TRI && !mat_tensor(LA, LB)) {
+        PtXY<T> *txy;
+        PtZ<T> *tz;
+        AxisBlock *bl;
+        int *cnt;
+        BlockRow *rows;
+        const int emax = sg.emax;
+        PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
+        pair_setup<false, T>(r, G, txy, tz, bl, emax, cnt);
+        __syncthreads();
+        const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
+        __syncthreads();
         T acc[NA * NB];
 #pragma unroll
         for (int i = 0; i < NA * NB; ++i) acc[i] = T(0);
@@ -1409,7 +1770,7 @@ k_mat(SegTable<PairSeg> tab)
             }
         };
         DirectVisit<T, decltype(body)> vis(body, r);
-        for_each_point<T>(txy, tz, emax, rows, nrows, Vb, vis);
+        for_each_point<T>(txy, tz, emax, rows, nrows, sg.Vb, vis);
         __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
         wave_reduce_emit<NA * NB, T>(acc, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
             const int i = k / NB, j = k - (k / NB) * NB;
@@ -1417,23 +1778,18 @@ k_mat(SegTable<PairSeg> tab)
             atomicAdd(&sg.out[(long long)(r.ao_b + j) * n_ao + r.ao_a + i], scale * v);
         });
     } else {
-        constexpr int L = LA + LB, K = ntab(L);
-        TensorVisit<L, T> vis(r);
-        for_each_point<T>(txy, tz, emax, rows, nrows, Vb, vis);
-        __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
-        // wave sums of the moments, kept in LDS past the reduction area
-        double *mom = reinterpret_cast<double *>(smem_raw) + 8 * 65;
-        wave_reduce_emit<K, T>(vis.Vm, reinterpret_cast<double *>(smem_raw),
-                               [&](int k, double v) { mom[k] = v; });
-        __syncthreads();
-        // element (i, j): the moments of (x-A)^a (x-B)^b with every
+        // the moments of the monomials of r - A up to degree l_a + l_b, then
+        // element (i, j) from the moments of (x-A)^a (x-B)^b with every
         // (x - B_x)^b_x expanded binomially around A (Eq. (binomial))
+        const double *mom = pair_moments<LA + LB, T, TRI>(sg, r, smem_raw);
+        double AB[3];
+        cart_ab(r, TRI ? G.tri : nullptr, AB);
         double ab[3][LB + 1];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             ab[d][0] = 1.0;
 #pragma unroll
-            for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * r.AB[d];
+            for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * AB[d];
         }
         constexpr int NE = NA * NB, NS = (NE + 63) / 64;
         double m[NS];
@@ -1517,40 +1873,23 @@ __device__ __forceinline__ void grad_elements(std::integer_sequence<int, E...>, 
      ...);
 }
 
-template <int LA, int LB, typename T>
+template <int LA, int LB, typename T, bool TRI = false>
 __global__ void __launch_bounds__(64)
 k_grad(SegTable<PairSeg> tab)
 {
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
-    constexpr int L1 = LA + LB + 1, K = ntab(L1);
     extern __shared__ unsigned char smem_raw[];
-    PtXY<T> *txy;
-    PtZ<T> *tz;
-    AxisBlock *bl;
-    int *cnt;
-    BlockRow *rows;
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const LevelGeom &G = sg.G;
-    const int n_ao = sg.n_ao, emax = sg.emax;
-    const double *__restrict__ Vb = sg.Vb;
-    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
+    const int n_ao = sg.n_ao;
     const PairRec &r = sg.pairs[item];
-    pair_setup<true, T>(r, G, txy, tz, bl, emax, cnt);
-    __syncthreads();
-    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
-    __syncthreads();
     // potential moments of the monomials of r - A up to degree l_a + l_b + 1
-    TensorVisit<L1, T> vis(r);
-    for_each_point<T>(txy, tz, emax, rows, nrows, Vb, vis);
-    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
-    double *red = reinterpret_cast<double *>(smem_raw);
-    double *mom = red + 8 * 65;
-    wave_reduce_emit<K, T>(vis.Vm, red, [&](int k, double v) { mom[k] = v; });
-    __syncthreads();
+    const double *mom = pair_moments<LA + LB + 1, T, TRI>(sg, r, smem_raw);
     const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
-    const double AB[3] = {r.AB[0], r.AB[1], r.AB[2]};
+    double AB[3];
+    cart_ab(r, TRI ? G.tri : nullptr, AB);
     double ab[3][LB + 1];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -1563,7 +1902,7 @@ k_grad(SegTable<PairSeg> tab)
                              n_ao, (int)threadIdx.x, g6);
     const double scale = G.w * r.Kw;
     __syncthreads();   // every read of the moments is done
-    wave_reduce_emit<6, double>(g6, red, [&](int k, double v) {
+    wave_reduce_emit<6, double>(g6, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
         atomicAdd(&sg.out[3 * (k < 3 ? r.atom_a : r.atom_b) + (k < 3 ? k : k - 3)], scale * v);
     });
 }
@@ -1712,38 +2051,11 @@ __device__ __forceinline__ void grad_tau_element(int i, int j, double two_a, dou
     }
 }
 
-// Moments of degree LT of one pair image (pair-major traversal), wave-summed
-// into LDS past the reduction area; returns their address.
-template <int LT, typename T>
-__device__ __forceinline__ const double *pair_moments(const PairSeg &sg, const PairRec &r, unsigned char *smem_raw)
-{
-    PtXY<T> *txy;
-    PtZ<T> *tz;
-    AxisBlock *bl;
-    int *cnt;
-    BlockRow *rows;
-    const LevelGeom &G = sg.G;
-    const int emax = sg.emax;
-    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
-    pair_setup<true, T>(r, G, txy, tz, bl, emax, cnt);
-    __syncthreads();
-    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
-    __syncthreads();
-    TensorVisit<LT, T> vis(r);
-    for_each_point<T>(txy, tz, emax, rows, nrows, sg.Vb, vis);
-    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
-    double *red = reinterpret_cast<double *>(smem_raw);
-    double *mom = red + 8 * 65;
-    wave_reduce_emit<ntab(LT), T>(vis.Vm, red, [&](int k, double v) { mom[k] = v; });
-    __syncthreads();
-    return mom;
-}
-
 // Kinetic-energy-density term of the matrix (the variational derivative of
 // E_tau = sum_l w_l <vtau_l, tau_l(D)>): M_ij += 1/2 w sum_r vtau grad a_i .
 // grad b_j (Sec. II, Eq. (J_metaGGA); Sec. III.B with Alg. 2), one wave per
 // pair image, both triangles.
-template <int LA, int LB, typename T>
+template <int LA, int LB, typename T, bool TRI = false>
 __global__ void __launch_bounds__(64)
 k_mat_tau(SegTable<PairSeg> tab)
 {
@@ -1753,8 +2065,9 @@ k_mat_tau(SegTable<PairSeg> tab)
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const PairRec &r = sg.pairs[item];
-    const double *mom = pair_moments<LA + LB + 2, T>(sg, r, smem_raw);
-    const double AB[3] = {r.AB[0], r.AB[1], r.AB[2]};
+    const double *mom = pair_moments<LA + LB + 2, T, TRI>(sg, r, smem_raw);
+    double AB[3];
+    cart_ab(r, TRI ? sg.G.tri : nullptr, AB);
     // 1/2 of the meta-GGA term times the 1/2 that splits Kw over both triangles
     const double scale = 0.25 * sg.G.w * r.Kw;
     const int n_ao = sg.n_ao;
@@ -1774,7 +2087,7 @@ k_mat_tau(SegTable<PairSeg> tab)
 // note with Alg. 3): second derivatives of the first factor and first
 // derivatives of the second, one lane per element weighted by the symmetrised
 // D_ij, a wave sum of the six components, atomics into the two atoms.
-template <int LA, int LB, typename T>
+template <int LA, int LB, typename T, bool TRI = false>
 __global__ void __launch_bounds__(64)
 k_grad_tau(SegTable<PairSeg> tab)
 {
@@ -1784,8 +2097,9 @@ k_grad_tau(SegTable<PairSeg> tab)
     const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
     if (item >= sg.count) return;
     const PairRec &r = sg.pairs[item];
-    const double *mom = pair_moments<LA + LB + 3, T>(sg, r, smem_raw);
-    const double AB[3] = {r.AB[0], r.AB[1], r.AB[2]};
+    const double *mom = pair_moments<LA + LB + 3, T, TRI>(sg, r, smem_raw);
+    double AB[3];
+    cart_ab(r, TRI ? sg.G.tri : nullptr, AB);
     const int n_ao = sg.n_ao;
     const T *Dp = (const T *)sg.Dm + (long long)r.ao_a * n_ao + r.ao_b;
     double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1870,7 +2184,14 @@ struct ClassLaunch {
     SegList<PackSeg> packs, tpacks;      // packed coefficients of rho / tau
     SegList<RhoSeg> rhos, taus;          // grid-block major collocation
     SegList<PairSeg> mats, grads, mtaus, gtaus;   // pair-major integration / gradient
+    // general cells: the density's coefficient tensors (every class), their
+    // rewrite on the index offset (rho and tau), and the kernels of index units
+    SegList<PackSeg> packs_t;
+    SegList<IdxSeg> idxs;
+    SegList<RhoSeg> rhos_t, taus_t;
+    SegList<PairSeg> mats_t, grads_t, mtaus_t, gtaus_t;
     size_t smem = 0;                     // LDS bytes of the pair-major kernels
+    size_t smem_t = 0;                   // the same, general cells
     hipStream_t st = nullptr;
     bool fp32 = false;                   // per-point arithmetic in float
 };

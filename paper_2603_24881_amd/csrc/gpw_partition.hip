@@ -73,10 +73,19 @@ k_pairs(PsTable ps, PlanConst pc, unsigned long long *group_cnt, const long long
     const double dmax = sqrt(Q / mu);
     long long nlo[3], nhi[3];
     double AB0[3];
+    for (int d = 0; d < 3; ++d) AB0[d] = A[d] - B[d];
     for (int d = 0; d < 3; ++d) {
-        AB0[d] = A[d] - B[d];
-        nlo[d] = (long long)ceil((AB0[d] - dmax) / pc.L[d]);
-        nhi[d] = (long long)floor((AB0[d] + dmax) / pc.L[d]);
+        if (pc.tri) {
+            // |A - B - T| <= dmax bounds the fractional coordinate of A - B - T
+            const double u = AB0[0] * pc.Ainv[0][d] + AB0[1] * pc.Ainv[1][d] + AB0[2] * pc.Ainv[2][d];
+            const double du = dmax * sqrt(pc.Ainv[0][d] * pc.Ainv[0][d] + pc.Ainv[1][d] * pc.Ainv[1][d] +
+                                          pc.Ainv[2][d] * pc.Ainv[2][d]);
+            nlo[d] = (long long)ceil(u - du) - 1;
+            nhi[d] = (long long)floor(u + du) + 1;
+        } else {
+            nlo[d] = (long long)ceil((AB0[d] - dmax) / pc.L[d]);
+            nhi[d] = (long long)floor((AB0[d] + dmax) / pc.L[d]);
+        }
     }
     const int lvl = level_for(pc, ap);
     const int g = lvl * kNCls + cls_of(la, lb);
@@ -86,9 +95,14 @@ k_pairs(PsTable ps, PlanConst pc, unsigned long long *group_cnt, const long long
                 if (i == j) {   // same primitive shell: keep T = 0 and one of +-T
                     if (n0 < 0 || (n0 == 0 && (n1 < 0 || (n1 == 0 && n2 < 0)))) continue;
                 }
-                const double t0 = AB0[0] - n0 * pc.L[0];
-                const double t1 = AB0[1] - n1 * pc.L[1];
-                const double t2 = AB0[2] - n2 * pc.L[2];
+                // A - B - T, T = n0 a_0 + n1 a_1 + n2 a_2
+                double Tv[3];
+                for (int c = 0; c < 3; ++c)
+                    Tv[c] = pc.tri ? n0 * pc.A[0][c] + n1 * pc.A[1][c] + n2 * pc.A[2][c]
+                                   : (c == 0 ? n0 * pc.L[0] : c == 1 ? n1 * pc.L[1] : n2 * pc.L[2]);
+                const double t0 = AB0[0] - Tv[0];
+                const double t1 = AB0[1] - Tv[1];
+                const double t2 = AB0[2] - Tv[2];
                 const double d2 = t0 * t0 + t1 * t1 + t2 * t2;
                 if (mu * d2 > Q) continue;
                 if (!FILL) {
@@ -104,21 +118,41 @@ k_pairs(PsTable ps, PlanConst pc, unsigned long long *group_cnt, const long long
                 const double wc = (i == j && n0 == 0 && n1 == 0 && n2 == 0) ? 1.0 : 2.0;
                 const double logK = logcc - mu * d2;
                 const double R = trunc_radius(logK, L, ap, pc.logtau);
-                const double Bp[3] = {B[0] + n0 * pc.L[0], B[1] + n1 * pc.L[1], B[2] + n2 * pc.L[2]};
+                const double Bp[3] = {B[0] + Tv[0], B[1] + Tv[1], B[2] + Tv[2]};
                 const LevelGeom &G = pc.geom[lvl];
+                const TriGeom *tg = G.tri;
                 for (int d = 0; d < 3; ++d) {
                     r.A[d] = A[d];
                     r.AB[d] = A[d] - Bp[d];
                     r.P[d] = (aa * A[d] + ab * Bp[d]) / ap;
-                    r.lo[d] = (int)ceil((r.P[d] - R) / G.h[d]);
-                    r.hi[d] = (int)floor((r.P[d] + R) / G.h[d]);
+                }
+                if (tg) {
+                    // a general cell: positions in the level's index coordinates s = r Hinv
+                    double sA[3], sAB[3], sP[3];
+                    for (int d = 0; d < 3; ++d) {
+                        sA[d] = r.A[0] * tg->Hinv[0][d] + r.A[1] * tg->Hinv[1][d] + r.A[2] * tg->Hinv[2][d];
+                        sAB[d] = r.AB[0] * tg->Hinv[0][d] + r.AB[1] * tg->Hinv[1][d] + r.AB[2] * tg->Hinv[2][d];
+                        sP[d] = r.P[0] * tg->Hinv[0][d] + r.P[1] * tg->Hinv[1][d] + r.P[2] * tg->Hinv[2][d];
+                    }
+                    for (int d = 0; d < 3; ++d) {
+                        r.A[d] = sA[d];
+                        r.AB[d] = sAB[d];
+                        r.P[d] = sP[d];
+                        r.lo[d] = (int)ceil(r.P[d] - R * tg->rf[d]);
+                        r.hi[d] = (int)floor(r.P[d] + R * tg->rf[d]);
+                    }
+                } else {
+                    for (int d = 0; d < 3; ++d) {
+                        r.lo[d] = (int)ceil((r.P[d] - R) / G.h[d]);
+                        r.hi[d] = (int)floor((r.P[d] + R) / G.h[d]);
+                    }
                 }
                 r.aa = aa;
                 r.ab = ab;
                 r.Kw = wc * ca * cb * exp(-mu * d2);
                 r.R2 = R * R;
                 r.ER = exp(-ap * R * R);
-                for (int d = 0; d < 3; ++d) r.c[d] = exp(-ap * G.h[d] * G.h[d]);
+                for (int d = 0; d < 3; ++d) r.c[d] = exp(-ap * (tg ? tg->g[d][d] : G.h[d] * G.h[d]));
                 for (int d = 0; d < 3; ++d) {
                     const int g0 = axis_block_id(r.lo[d], G.N[d], G.nb[d]);
                     r.bs0[d] = floordiv(g0, G.nb[d]);
@@ -162,22 +196,26 @@ k_incidences(const PairRec *pairs, long long npairs, PlanConst pc, const long lo
     const int g = r.level * kNCls + r.cls;
     const double R2c = r.R2 * kCullSlack;
     const long long base = cnt_base_g[g];
+    // per-axis gaps in Cartesian units (orthorhombic), or in index units scaled
+    // by the metric's smallest eigenvalue (a general cell: their sum stays below
+    // the block's true squared distance, so the cull is conservative)
+    const double gs = G.tri ? G.tri->lmin : 1.0;
     long long ninc = 0;
     AxisIter ix, iy, iz;
     for (ix.start(r.lo[0], r.hi[0], G.N[0], G.nb[0]); ix.valid(); ix.next()) {
         double x0, x1;
         ix.range(G.h[0], x0, x1);
-        const double gx = axis_gap2(r.P[0], x0, x1);
+        const double gx = gs * axis_gap2(r.P[0], x0, x1);
         if (gx > R2c) continue;
         for (iy.start(r.lo[1], r.hi[1], G.N[1], G.nb[1]); iy.valid(); iy.next()) {
             double y0, y1;
             iy.range(G.h[1], y0, y1);
-            const double gy = gx + axis_gap2(r.P[1], y0, y1);
+            const double gy = gx + gs * axis_gap2(r.P[1], y0, y1);
             if (gy > R2c) continue;
             for (iz.start(r.lo[2], r.hi[2], G.N[2], G.nb[2]); iz.valid(); iz.next()) {
                 double z0, z1;
                 iz.range(G.h[2], z0, z1);
-                if (gy + axis_gap2(r.P[2], z0, z1) > R2c) continue;
+                if (gy + gs * axis_gap2(r.P[2], z0, z1) > R2c) continue;
                 const long long b = block_slot(G, (int)ix.k, (int)iy.k, (int)iz.k);
                 if (ix.S < -127 || ix.S > 127 || iy.S < -127 || iy.S > 127 || iz.S < -127 || iz.S > 127) {
                     atomicOr(err_flag, 2);   // fold shift does not fit the packed entry
@@ -202,11 +240,24 @@ k_incidences(const PairRec *pairs, long long npairs, PlanConst pc, const long lo
             const double dx = (double)ux * G.h[0] - r.P[0];
             for (int uy = r.lo[1]; uy <= r.hi[1]; ++uy) {
                 const double dy = (double)uy * G.h[1] - r.P[1];
-                const double rem = r.R2 - dx * dx - dy * dy;
-                if (rem < 0.0) continue;
-                const double zr = sqrt(rem);
-                const long long z0 = (long long)ceil((r.P[2] - zr) / G.h[2]);
-                const long long z1 = (long long)floor((r.P[2] + zr) / G.h[2]);
+                long long z0, z1;
+                if (G.tri) {
+                    // (dx, dy, dz) g (dx, dy, dz)^T <= R^2, a quadratic in dz
+                    const double(*gm)[3] = G.tri->g;
+                    const double qa = gm[2][2], qb = 2.0 * (gm[0][2] * dx + gm[1][2] * dy);
+                    const double qc = gm[0][0] * dx * dx + 2.0 * gm[0][1] * dx * dy + gm[1][1] * dy * dy - r.R2;
+                    const double disc = qb * qb - 4.0 * qa * qc;
+                    if (disc < 0.0) continue;
+                    const double sq = sqrt(disc);
+                    z0 = (long long)ceil(r.P[2] + (-qb - sq) / (2.0 * qa));
+                    z1 = (long long)floor(r.P[2] + (-qb + sq) / (2.0 * qa));
+                } else {
+                    const double rem = r.R2 - dx * dx - dy * dy;
+                    if (rem < 0.0) continue;
+                    const double zr = sqrt(rem);
+                    z0 = (long long)ceil((r.P[2] - zr) / G.h[2]);
+                    z1 = (long long)floor((r.P[2] + zr) / G.h[2]);
+                }
                 if (z1 >= z0) npts += z1 - z0 + 1;
             }
         }
@@ -246,7 +297,8 @@ k_cell_count(const PairRec *pairs, long long n, PlanConst pc, unsigned *hist, un
     const PairRec &r = pairs[p];
     unsigned c[3];
     for (int d = 0; d < 3; ++d) {
-        double f = r.P[d] / pc.L[d];
+        // fractional coordinate of the product centre (index units / N for a general cell)
+        double f = pc.tri ? r.P[d] / pc.geom[r.level].N[d] : r.P[d] / pc.L[d];
         f -= floor(f);
         int ci = (int)(f * (1 << kCellBits));
         c[d] = (unsigned)min(max(ci, 0), (1 << kCellBits) - 1);

@@ -8,7 +8,9 @@
 //   v_l(r)   = (1 / Omega) sum_G mask_l(G) v~(G) exp(i G.r)
 //   E_J      = (1 / (2 Omega)) sum_{G != 0} 4 pi |rho~(G)|^2 / |G|^2
 // with mask_l(G): |m_d| < N_{l,d} / 2 on every axis (no Nyquist plane) and
-// |G|^2 < E_l, G = 2 pi m / L.  The densities are real, so each level works on
+// |G|^2 < E_l, G = sum_d m_d b_d with the reciprocal vectors
+// b_d = 2 pi (A^-1)[:, d] of the lattice vectors A (rows); G = 2 pi m / L for
+// an orthorhombic cell.  The densities are real, so each level works on
 // its half spectrum (m_z >= 0, hipFFT D2Z / Z2D); the coefficients of all
 // levels meet on the half spectrum of the finest mesh, where a level's
 // plane wave m sits at (m_x mod N_0x, m_y mod N_0y, m_z).  The energy sums the
@@ -39,10 +41,17 @@ constexpr int kEnergyBlocks = 1024;
 // above n / 2; the Nyquist index of an even n maps to -n / 2).
 __device__ __forceinline__ int freq_of(int i, int n) { return 2 * i < n ? i : i - n; }
 
+// Cartesian G = sum_d m_d b_d; B[d] holds b_d
+__device__ __forceinline__ void gvec(int mx, int my, int mz, const double (*B)[3], double *g)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = mx * B[0][c] + my * B[1][c] + mz * B[2][c];
+}
+
 // The level's masked plane wave at half-spectrum index i, as a fine-grid
 // half-spectrum index, or -1.
 __device__ __forceinline__ long long level_to_fine(long long i, const LevelGeom &G, const int *Nf, double cut,
-                                                   const double *L)
+                                                   const double (*B)[3])
 {
     const int nzh = G.N[2] / 2 + 1;
     const int iz = (int)(i % nzh);
@@ -51,8 +60,9 @@ __device__ __forceinline__ long long level_to_fine(long long i, const LevelGeom 
     const int mx = freq_of(ix, G.N[0]), my = freq_of(iy, G.N[1]), mz = iz;
     if (2 * abs(mx) >= G.N[0] || 2 * abs(my) >= G.N[1] || 2 * mz >= G.N[2]) return -1;
     if (cut > 0.0) {
-        const double gx = 2.0 * M_PI * mx / L[0], gy = 2.0 * M_PI * my / L[1], gz = 2.0 * M_PI * mz / L[2];
-        if (!(gx * gx + gy * gy + gz * gz < cut)) return -1;
+        double g[3];
+        gvec(mx, my, mz, B, g);
+        if (!(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] < cut)) return -1;
     }
     const int fx = mx < 0 ? mx + Nf[0] : mx, fy = my < 0 ? my + Nf[1] : my;
     return ((long long)fx * Nf[1] + fy) * (Nf[2] / 2 + 1) + mz;
@@ -61,7 +71,7 @@ __device__ __forceinline__ long long level_to_fine(long long i, const LevelGeom 
 struct PoissonGeom {
     LevelGeom G;          // this level
     int Nf[3];            // the finest mesh
-    double L[3];
+    double B[3][3];       // reciprocal vectors b_d (rows), 2 pi (A^-1)^T
     double cut;           // Ry, or 0 for every plane wave of the mesh
     double scale;         // w_l (scatter) or 1 / Omega (gather)
 };
@@ -78,7 +88,7 @@ __global__ void __launch_bounds__(256) k_scatter(const double2 *__restrict__ c, 
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= half_count(pg.G)) return;
-    const long long f = level_to_fine(i, pg.G, pg.Nf, pg.cut, pg.L);
+    const long long f = level_to_fine(i, pg.G, pg.Nf, pg.cut, pg.B);
     if (f < 0) return;
     const double2 a = c[i];
     double2 b = fine[f];
@@ -92,7 +102,7 @@ __global__ void __launch_bounds__(256) k_gather(const double2 *__restrict__ fine
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= half_count(pg.G)) return;
-    const long long f = level_to_fine(i, pg.G, pg.Nf, pg.cut, pg.L);
+    const long long f = level_to_fine(i, pg.G, pg.Nf, pg.cut, pg.B);
     double2 v = make_double2(0.0, 0.0);
     if (f >= 0) {
         const double2 a = fine[f];
@@ -115,10 +125,9 @@ __global__ void __launch_bounds__(256) k_coulomb(double2 *__restrict__ fine, dou
         const int iz = (int)(i % nzh);
         const long long r = i / nzh;
         const int iy = (int)(r % N[1]), ix = (int)(r / N[1]);
-        const double gx = 2.0 * M_PI * freq_of(ix, N[0]) / pg.L[0];
-        const double gy = 2.0 * M_PI * freq_of(iy, N[1]) / pg.L[1];
-        const double gz = 2.0 * M_PI * iz / pg.L[2];
-        const double g2 = gx * gx + gy * gy + gz * gz;
+        double g[3];
+        gvec(freq_of(ix, N[0]), freq_of(iy, N[1]), iz, pg.B, g);
+        const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
         const double coul = g2 > 0.0 ? 4.0 * M_PI / g2 : 0.0;
         const double2 a = fine[i];
         acc += (iz == 0 ? 1.0 : 2.0) * coul * (a.x * a.x + a.y * a.y);
@@ -148,15 +157,14 @@ __global__ void __launch_bounds__(256) k_energy(const double *__restrict__ parti
     if (threadIdx.x == 0) *ej = red[0] * inv2vol;
 }
 
-// G_d of fine half-spectrum index i
-__device__ __forceinline__ double fine_g(long long i, const int *N, const double *L, int d)
+// Cartesian component d of G at fine half-spectrum index i
+__device__ __forceinline__ double fine_g(long long i, const int *N, const double (*B)[3], int d)
 {
     const int nzh = N[2] / 2 + 1;
     const int iz = (int)(i % nzh);
     const long long r = i / nzh;
     const int iy = (int)(r % N[1]), ix = (int)(r / N[1]);
-    const int m = d == 0 ? freq_of(ix, N[0]) : d == 1 ? freq_of(iy, N[1]) : iz;
-    return 2.0 * M_PI * m / L[d];
+    return freq_of(ix, N[0]) * B[0][d] + freq_of(iy, N[1]) * B[1][d] + iz * B[2][d];
 }
 
 // out = scale * (i G_d)^k * fine on the fine half spectrum (k = 0 or 1, d < 0
@@ -171,7 +179,7 @@ __global__ void __launch_bounds__(256) k_fine_out(const double2 *__restrict__ fi
     if (d < 0) {
         out[i] = make_double2(pg.scale * a.x, pg.scale * a.y);
     } else {
-        const double g = pg.scale * fine_g(i, pg.Nf, pg.L, d);   // i g (a.x + i a.y) = -g a.y + i g a.x
+        const double g = pg.scale * fine_g(i, pg.Nf, pg.B, d);   // i g (a.x + i a.y) = -g a.y + i g a.x
         out[i] = make_double2(-g * a.y, g * a.x);
     }
 }
@@ -184,14 +192,14 @@ __global__ void __launch_bounds__(256) k_add_xc(const double2 *__restrict__ c, d
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= half_count(pg.G)) return;
-    if (level_to_fine(i, pg.G, pg.Nf, pg.cut, pg.L) < 0) return;   // level 0's own mask: f == i
+    if (level_to_fine(i, pg.G, pg.Nf, pg.cut, pg.B) < 0) return;   // level 0's own mask: f == i
     const double2 a = c[i];
     double2 b = fine[i];
     if (d < 0) {
         b.x += pg.scale * a.x;
         b.y += pg.scale * a.y;
     } else {
-        const double g = pg.scale * fine_g(i, pg.Nf, pg.L, d);   // -i g (a.x + i a.y) = g a.y - i g a.x
+        const double g = pg.scale * fine_g(i, pg.Nf, pg.B, d);   // -i g (a.x + i a.y) = g a.y - i g a.x
         b.x += g * a.y;
         b.y -= g * a.x;
     }
@@ -281,7 +289,7 @@ static PoissonGeom base_geom(const gpw_plan_s *pl)
     PoissonGeom pg{};
     for (int d = 0; d < 3; ++d) {
         pg.Nf[d] = pl->geom[0].N[d];
-        pg.L[d] = pl->L[d];
+        for (int c = 0; c < 3; ++c) pg.B[d][c] = pl->recip[d][c];
     }
     return pg;
 }
@@ -316,7 +324,7 @@ hipError_t poisson_run(gpw_plan_s *pl, const double *const *rho, const double *v
     PoissonScratch x;
     e = scratch_alloc(pl, ps, x, st);
     if (e != hipSuccess) return e;
-    const double vol = pl->L[0] * pl->L[1] * pl->L[2];
+    const double vol = pl->volume;
     PoissonGeom pg = base_geom(pl);
     {
         // the FFT plans are shared by every caller of this plan: set their
@@ -366,7 +374,7 @@ hipError_t fine_density_run(gpw_plan_s *pl, const double *const *rho, double *rh
     PoissonScratch x;
     e = scratch_alloc(pl, ps, x, st);
     if (e != hipSuccess) return e;
-    const double vol = pl->L[0] * pl->L[1] * pl->L[2];
+    const double vol = pl->volume;
     PoissonGeom pg = base_geom(pl);
     pg.G = pl->geom[0];
     pg.scale = 1.0 / vol;

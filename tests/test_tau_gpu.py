@@ -68,7 +68,7 @@ def test_tiny_spdf_all_classes(mesh):
     s = tiny.tiny_system(mesh=(mesh,), tau=1e-10)
     o = oracle.Oracle(s)
     info = _compare(s, tiny.random_density(s.n_ao), synth.make_potentials(o.meshes, 21))
-    assert all(c > 0 for c in info["n_pairs_class"]), info["n_pairs_class"]
+    assert all(c > 0 for c in info["n_pairs_class"][:10]), info["n_pairs_class"]
 
 
 def test_tiny_spdfg_all_fifteen_classes():
