@@ -47,8 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-atoms", type=int, default=0, help="atoms in the oracle sample (0 = auto)")
     ap.add_argument("--extras", type=int, default=1, help="also time grad, fp32 and the plan")
-    ap.add_argument("--serve-requests", type=int, default=120, help="requests in the serving run (0 = skip)")
-    ap.add_argument("--serve-rates", default="20,100,200", help="Poisson arrival rates (requests/s), comma-separated")
+    ap.add_argument("--serve-requests", type=int, default=600, help="requests in the serving run (0 = skip)")
+    ap.add_argument("--serve-rates", default="20,50,100,200", help="Poisson arrival rates (requests/s), comma-separated")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters) and exit")
@@ -239,7 +239,8 @@ def serving(n, rates, budget_gb):
     reg = time.perf_counter() - t0
     log(f"[bench] serving: 12 plans registered in {reg:.1f} s")
     out = {"requests": n, "sizes_waters": list(sizes), "geometries": 2, "grad_fraction": 0.5,
-           "budget_gb": budget_gb, "max_active": 16, "plan_register_s": round(reg, 2), "runs": []}
+           "budget_gb": budget_gb, "max_active": 32, "max_batch": 16, "lanes": ex.n_lanes,
+           "plan_register_s": round(reg, 2), "runs": []}
     warm = poisson_trace(24, 1000.0, seed=1999)
     Scheduler(ex, budget_gb * 2 ** 30).run(warm)
     for rate in rates:
@@ -251,7 +252,7 @@ def serving(n, rates, budget_gb):
             sm = summarize(trace)
             if mode == "continuous":
                 sm["rounds"] = len(sch.rounds)
-                sm["mean_tasks_per_round"] = float(np.mean([a + b for a, b in sch.rounds]))
+                sm["mean_requests_per_round"] = float(np.mean(sch.rounds))
             run[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()}
             log(f"[bench] serving {rate:g}/s {mode}: {run[mode]}")
         out["runs"].append(run)

@@ -6,28 +6,34 @@ Coulomb matrix J = eval_mat(v_H) and E_J; a gradient request returns
 dE_J/dR = eval_grad(D, v_H) and E_J, where v_H is the Hartree potential of
 rho = eval_rho(D) from the multigrid Poisson step.
 
-The scheduler runs rounds.  In every round one ``gpw_eval_batch`` call
-carries the collocation task of every request admitted since the last round
-and the integration (or gradient) task of every request that finished its
-collocation in the previous round, so requests of different systems and
-sizes share the same launches; after the batch the Poisson step of the new
-requests runs.  A request therefore completes in two rounds, or in one when
-no other request is waiting as the round starts (then the new requests' second
-stage follows in the same round and there is nothing to batch it with anyway).
-Requests that
-arrive while a round is on the device are admitted at the start of the next
-round, in arrival order, as long as the number of requests starting their
-first stage in the round stays within ``max_active`` and their device memory
-(plus that of their plan, when it is not resident) fits the HBM budget; idle plans are evicted least
-recently used first to make room.  A request that can never fit is
-rejected.
+The server keeps a few lanes, each a device stream.  Whenever a lane is free
+and admitted requests are waiting, the lane takes a batch of them and runs
+their whole request as one round: one ``gpw_eval_batch`` call with the
+collocation of every request in the batch (requests of different systems and
+sizes share the same launches), the Poisson step of each, one
+``gpw_eval_batch`` call with the integration or gradient of each, and an
+event at the end.  Rounds on different lanes run on the device at the same
+time, so a small request does not wait behind a large one while a lane is
+free.  The host loop never blocks on the device: it polls the lanes' events,
+hands results back as soon as their round has completed (that is the time
+a request is stamped done), admits arrivals while rounds run, and otherwise
+sleeps until the next arrival or completion.  Admission is in arrival order,
+while the number of admitted, unfinished requests stays within
+``max_active`` and their device memory (plus that of their plan, when it is
+not resident) fits the HBM budget; idle plans are evicted least recently
+used first to make room.  A request that can never fit is rejected.  With
+several free lanes the waiting requests are split between them; a batch
+holds at most ``max_batch`` requests, of work estimates within
+``group_ratio`` of the oldest waiting request's (a small request then does
+not wait for a large one that shares its round).
 
 ``run_sequential`` is the baseline: the same requests, one at a time in
-arrival order, with the plain single calls.
+arrival order, with the plain single calls, each stamped done after the
+device has finished it.
 
 The scheduler talks to an executor (``GPUExecutor`` here; tests use a
-simulated one) through: register, plan_bytes, request_bytes, load, unload,
-begin, round, single, end, now, sleep_until.
+simulated one) through: n_lanes, cost, plan_bytes, request_bytes, load,
+unload, begin, launch, done, wait, single, end, now, sleep_until.
 """
 from __future__ import annotations
 
@@ -79,14 +85,18 @@ def system_key(n_waters, geometry):
 
 
 class Scheduler:
-    def __init__(self, executor, budget_bytes, max_active=16):
+    def __init__(self, executor, budget_bytes, max_active=32, max_batch=16, group_ratio=2.0):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
+        self.max_batch = int(max_batch)
+        self.group_ratio = group_ratio
+        self.lanes = int(executor.n_lanes)
         self.used = 0
+        self.n_active = 0                 # admitted, not yet done
         self.resident = OrderedDict()     # key -> plan bytes, least recently used first
         self.users = {}                   # key -> active requests on that plan
-        self.rounds = []                  # per round: (n collocation tasks, n integration tasks)
+        self.rounds = []                  # per launched round: number of requests
 
     # ---------------------------------------------------------- memory
     def _need(self, r):
@@ -121,12 +131,11 @@ class Scheduler:
     def _release(self, r):
         self.used -= self.ex.request_bytes(r.system, r.kind)
         self.users[r.system] -= 1
+        self.n_active -= 1
 
-    def _admit(self, pending, active, now):
-        # at the start of a round every active request is in its second stage
-        # and leaves with this round: the slots limit the new (first-stage) ones
-        new = sum(1 for r in active if r.stage == 0)
-        while pending and pending[0].arrival <= now and new < self.max_active:
+    def _admit(self, pending, queue, now):
+        """Admit the arrived requests in arrival order while slots and memory allow."""
+        while pending and pending[0].arrival <= now and self.n_active < self.max_active:
             r = pending[0]
             if not self._fits_ever(r):
                 pending.popleft()
@@ -137,39 +146,75 @@ class Scheduler:
             pending.popleft()
             r.admitted = now
             r.stage = 0
+            self.n_active += 1
             self.ex.begin(r)
-            active.append(r)
-            new += 1
+            queue.append(r)
+
+    def _limit(self, lane):
+        lim = self.ex.lane_limit(lane)
+        return math.inf if lim is None else lim
+
+    def _group(self, queue, limit=math.inf):
+        """The waiting requests that may share a round on a lane that takes
+        work estimates up to limit: the oldest eligible one and those whose
+        estimate is within group_ratio of its own (every eligible one with
+        group_ratio None), in arrival order, so that a small request is not
+        held until a large one in its round completes."""
+        elig = [r for r in queue if self.ex.cost(r.system) <= limit]
+        if not elig or self.group_ratio is None:
+            return elig
+        c0 = self.ex.cost(elig[0].system)
+        lo, hi = c0 / self.group_ratio, c0 * self.group_ratio
+        return [r for r in elig if lo <= self.ex.cost(r.system) <= hi]
 
     # ---------------------------------------------------------- runs
     def run(self, requests):
         """Continuous batching; returns the requests with times and results."""
         pending = deque(sorted(requests, key=lambda q: (q.arrival, q.rid)))
-        active = []
+        queue = []        # admitted, waiting for a lane
+        busy = {}         # lane -> (round handle, its requests)
         t0 = self.ex.now()
-        while pending or active:
-            self._admit(pending, active, self.ex.now() - t0)
-            if not active:
-                if pending:
-                    self.ex.sleep_until(t0 + pending[0].arrival)
-                continue
-            s0 = [r for r in active if r.stage == 0]
-            s1 = [r for r in active if r.stage == 1]
-            # nobody waiting: the new requests finish in this round too
-            fuse = not (pending and pending[0].arrival <= self.ex.now() - t0)
-            t_s1 = self.ex.round(s0, s1, fuse)
-            now = self.ex.now() - t0
-            self.rounds.append((len(s0), len(s1)))
-            for r in s1 + (s0 if fuse else []):
-                # second-stage results are complete when the round's batch is,
-                # before the new requests' Poisson steps
-                r.done = t_s1 - t0 if (t_s1 is not None and r.stage == 1) else now
-                self.ex.end(r)
-                self._release(r)
-                active.remove(r)
-            if not fuse:
-                for r in s0:
+        while pending or queue or busy:
+            # results of completed rounds, handed back as soon as the host sees them
+            for lane in sorted(busy):
+                h, batch = busy[lane]
+                if self.ex.done(h):
+                    t = self.ex.now() - t0
+                    for r in batch:
+                        r.done = t
+                        self.ex.end(r)
+                        self._release(r)
+                    del busy[lane]
+            self._admit(pending, queue, self.ex.now() - t0)
+            launched = False
+            # the most restricted free lanes choose first
+            free = sorted((lane for lane in range(self.lanes) if lane not in busy), key=self._limit)
+            for lane in free:
+                if not queue:
+                    break
+                group = self._group(queue, self._limit(lane))
+                if not group:
+                    continue
+                # split the group between the free lanes that may take it
+                c = self.ex.cost(group[0].system)
+                n_free = sum(1 for x in free if x not in busy and self._limit(x) >= c)
+                k = min(self.max_batch, -(-len(group) // max(1, n_free)))
+                batch = group[:k]
+                for r in batch:
+                    queue.remove(r)
                     r.stage = 1
+                busy[lane] = (self.ex.launch(batch, lane), batch)
+                self.rounds.append(len(batch))
+                launched = True
+            if launched:
+                continue
+            now = self.ex.now() - t0
+            t_next = t0 + pending[0].arrival if pending and pending[0].arrival > now else None
+            if not busy and t_next is None:
+                if pending and not queue:
+                    raise RuntimeError("budget accounting: an idle server cannot admit a fitting request")
+                continue
+            self.ex.wait(t_next, [h for h, _ in busy.values()])
         return requests
 
     def run_sequential(self, requests):
@@ -184,6 +229,7 @@ class Scheduler:
             if not self._reserve(r):
                 raise RuntimeError("budget accounting: an idle server cannot admit a fitting request")
             r.admitted = self.ex.now() - t0
+            self.n_active += 1
             self.ex.begin(r)
             self.ex.single(r)
             r.done = self.ex.now() - t0
@@ -210,9 +256,13 @@ class GPUExecutor:
     """Runs requests on one device through the C ABI.  Plans are built at
     ``register`` (their size is then known, and the FFT plans of their Poisson
     step are built and warmed up) and stay resident until the scheduler
-    unloads them."""
+    unloads them.  Each lane is a device stream of default priority; E_J of
+    every request is copied into a pinned host slot on its lane, so that the
+    host reads it without waiting for the stream."""
 
-    def __init__(self, device=0, precision="fp64", keep_results=False):
+    N_SLOTS = 4096
+
+    def __init__(self, device=0, precision="fp64", keep_results=False, lanes=2, light_fraction=1.0 / 3.0):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -224,6 +274,12 @@ class GPUExecutor:
         self.sizes = {}         # key -> plan bytes
         self.req_sizes = {}     # key -> {kind: bytes}
         self.n_occ = {}
+        self.costs = {}         # key -> work estimate
+        self.n_lanes = int(lanes)
+        self.light_fraction = light_fraction
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
+        self.pinned = torch.zeros(self.N_SLOTS, dtype=torch.float64, pin_memory=True)
+        self.free_slots = list(range(self.N_SLOTS - 1, -1, -1))
 
     def register(self, key, system, resident=True):
         from .gpw import GPW
@@ -244,13 +300,15 @@ class GPUExecutor:
         # block-ordered potentials, with their periodic column extension, of the
         # integration and the gradient; the symmetrised D of the gradient)
         scr_rho, scr_mat, scr_grad = (int(x) for x in info["scratch_bytes"][:3])
-        # D, the level densities and then potentials, the Poisson step's
-        # spectra and FFT work area; the collocation's and the second stage's
-        # scratch never coexist within one request
+        # D, the level densities and the potentials, the Poisson step's spectra
+        # and FFT work area, the output, and the scratch of both stages (a
+        # batch's collocation and second stage are enqueued back to back, so
+        # their stream-ordered scratch can be live together)
         common = n2 + 2 * grids + poisson_bytes
-        self.req_sizes[key] = {FOCK: common + n2 + max(scr_rho, scr_mat),
-                               GRAD: common + 24 * info["natm"] + max(scr_rho, scr_grad)}
+        self.req_sizes[key] = {FOCK: common + n2 + scr_rho + scr_mat,
+                               GRAD: common + 24 * info["natm"] + scr_rho + scr_grad}
         self.n_occ[key] = system.n_occ
+        self.costs[key] = float(info["flops_rho_exec"] + info["flops_mat_exec"])
         if resident:
             self.plans[key] = (g, p)
         else:
@@ -262,6 +320,20 @@ class GPUExecutor:
 
     def request_bytes(self, key, kind):
         return self.req_sizes[key][kind]
+
+    def cost(self, key):
+        """Work estimate of a request on this system: the plan's FP64 work
+        of eval_rho and eval_mat."""
+        return self.costs[key]
+
+    def lane_limit(self, lane):
+        """Largest work estimate a lane takes: lane 0 any, the others the
+        light requests (up to light_fraction of the largest registered
+        system's), so that heavy requests run one round at a time, in arrival
+        order, and light ones beside them."""
+        if lane == 0 or self.light_fraction is None:
+            return None
+        return self.light_fraction * max(self.costs.values())
 
     def load(self, key):
         if key not in self.plans:
@@ -275,7 +347,8 @@ class GPUExecutor:
         g.close()
 
     def density(self, key, seed):
-        """D = C C^T, C an n_ao x n_occ N(0,1) matrix drawn on the device."""
+        """D = C C^T, C an n_ao x n_occ N(0,1) matrix drawn on the device (on
+        the current stream)."""
         torch = self.torch
         g, _ = self.plans[key]
         gen = torch.Generator(device=self.dev)
@@ -284,15 +357,21 @@ class GPUExecutor:
         return (C @ C.T).contiguous()
 
     def begin(self, r):
+        r.state = {"slot": self.free_slots.pop()}
+
+    def _first_stage_inputs(self, r):
         g, _ = self.plans[r.system]
-        r.state = {"D": self.density(r.system, r.seed), "rho": g.new_grids()}
+        r.state["D"] = self.density(r.system, r.seed)
+        r.state["rho"] = g.new_grids()
 
     def _finish_poisson(self, r):
         _, p = self.plans[r.system]
         v, e = p.solve_async(r.state["rho"])
         r.state["v"] = v
-        r.state["E_J"] = e          # device scalar, read when the request ends
         del r.state["rho"]
+        # E_J to the request's pinned host slot, in stream order
+        slot = r.state["slot"]
+        self.pinned[slot:slot + 1].copy_(e, non_blocking=True)
 
     def _output(self, r):
         torch = self.torch
@@ -309,40 +388,47 @@ class GPUExecutor:
             return dict(plan=g.plan, op=_lib.GPW_OP_MAT, v=r.state["v"], out=out)
         return dict(plan=g.plan, op=_lib.GPW_OP_GRAD, D=r.state["D"], v=r.state["v"], out=out)
 
-    def round(self, s0, s1, finish_new=False):
-        """The second stage of s1 as one batch, then the collocation of s0 as
-        another, queued back to back, then the Poisson steps of s0 (and, with
-        finish_new, their second stage).  Returns the time at which the s1
-        results were complete (None without s1), read from a stream event so
-        that the s0 work is not held back by a synchronisation."""
+    def launch(self, batch, lane):
+        """Enqueue the batch's round on the lane's stream: its density matrices
+        and grids, one collocation batch, the Poisson steps, one integration /
+        gradient batch; returns the event recorded at the round's end."""
         from . import _lib
         torch = self.torch
-        if finish_new and len(s0) == 1 and not s1:
-            # a lone request: the plain calls, as the one-at-a-time server makes them
-            self.single(s0[0])
-            return None
-        t_h0 = self.now()
-        ev0 = ev1 = None
-        if s1:
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ev0.record()
-            _lib.gpw_eval_batch([self._second_stage(r) for r in s1])
-            ev1.record()
-        if s0:
+        st = self.streams[lane]
+        with torch.cuda.stream(st):
+            for r in batch:
+                self._first_stage_inputs(r)
             tasks = []
-            for r in s0:
+            for r in batch:
                 g, _ = self.plans[r.system]
                 tasks.append(dict(plan=g.plan, op=_lib.GPW_OP_RHO, D=r.state["D"], rho=r.state["rho"]))
             _lib.gpw_eval_batch(tasks)
-        for r in s0:
-            self._finish_poisson(r)
-        if finish_new and s0:
-            _lib.gpw_eval_batch([self._second_stage(r) for r in s0])
-        torch.cuda.synchronize(self.dev)
-        return t_h0 + ev0.elapsed_time(ev1) * 1e-3 if s1 else None
+            for r in batch:
+                self._finish_poisson(r)
+            _lib.gpw_eval_batch([self._second_stage(r) for r in batch])
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return ev
+
+    def done(self, ev):
+        return ev.query()
+
+    def wait(self, t_next, events, tick=5e-5):
+        """Until an event has completed or the clock reaches t_next (None: no
+        arrival pending), polling every tick seconds."""
+        while True:
+            if any(ev.query() for ev in events):
+                return
+            now = time.perf_counter()
+            if t_next is not None and now >= t_next:
+                return
+            time.sleep(tick if t_next is None else max(0.0, min(tick, t_next - now)))
 
     def single(self, r):
+        """The plain calls of one request on the current stream, then a device
+        synchronisation."""
         g, _ = self.plans[r.system]
+        self._first_stage_inputs(r)
         g.rho(r.state["D"], out=r.state["rho"])
         self._finish_poisson(r)
         out = self._output(r)
@@ -354,7 +440,9 @@ class GPUExecutor:
 
     def end(self, r):
         key = "J" if r.kind == FOCK else "grad"
-        r.result = {"E_J": float(r.state["E_J"].item())}
+        slot = r.state["slot"]
+        r.result = {"E_J": float(self.pinned[slot])}
+        self.free_slots.append(slot)
         if self.keep:
             r.result[key] = r.state["out"]
         r.state = {}
