@@ -169,7 +169,9 @@ typedef struct {
  * arguments (including linearly dependent lattice vectors), GPW_EUNSUPPORTED
  * for l > 4, or a truncation
  * sphere too wide for the kernels (more than 1024 points per axis, more than
- * 127 cell periods, or point tables beyond one workgroup's LDS), GPW_ENOMEM,
+ * 127 cell periods, or per-axis point tables beyond one workgroup's LDS; the
+ * block rows of a wide sphere are walked in slices and never limit it),
+ * GPW_ENOMEM,
  * GPW_EDEVICE. */
 gpw_status gpw_plan(const gpw_cell *cell, const gpw_basis *basis,
                     const gpw_cutoffs *cut, gpw_plan_t *out);

@@ -262,6 +262,7 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                     q.out = t.out;
                     q.n_ao = pl->n_ao;
                     q.emax = emax;
+                    q.row_cap = row_capacity(emax);
                     q.vz = block_column(pl, l);
                     q.G = pl->geom[l];
                     if (pl->tri)

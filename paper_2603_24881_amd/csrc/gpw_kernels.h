@@ -107,6 +107,7 @@ struct PairSeg {
     const double *Vb;            // block-ordered level potential, vz blocks per (x, y) column
     double *out;                 // mat: M; grad: natm x 3
     int n_ao, emax, vz;
+    int row_cap;                 // block rows the LDS holds (row_capacity(emax))
     LevelGeom G;
 };
 
@@ -1233,23 +1234,25 @@ struct BlockRow {
     int zn;    // zlo | n << 16
 };
 
-// Rows of the pair image's blocks, in (x block, y block) order: built by the
-// wave with one candidate row per lane and a ballot compaction.
+// Rows of the pair image's blocks with x entries in [ex0, ex1), in (x block,
+// y block) order: built by the wave with one candidate row per lane and a
+// ballot compaction.
 __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, int vz, const AxisBlock *bl,
-                                          int emax, const int *cnt, BlockRow *rows)
+                                          int emax, const int *cnt, BlockRow *rows, int ex0, int ex1)
 {
     const int lane = threadIdx.x;
-    const int nx = uni(cnt[0]), ny = uni(cnt[1]), nz = uni(cnt[2]), em = uni(cnt[3]);
+    const int ny = uni(cnt[1]), nz = uni(cnt[2]), em = uni(cnt[3]);
+    const int ncand = (ex1 - ex0) * ny;
     const AxisBlock *blx = bl, *bly = bl + emax, *blz = bl + 2 * emax;
     const float rny = 1.0f / (float)ny;
     int nrows = 0;
-    for (int base = 0; base < nx * ny; base += 64) {
+    for (int base = 0; base < ncand; base += 64) {
         const int i = base + lane;
         bool ok = false;
         BlockRow row;
-        if (i < nx * ny) {
+        if (i < ncand) {
             // i / ny in single precision: exact while i and ny stay far below 2^20
-            const int ex = (int)(((float)i + 0.5f) * rny), ey = i - ex * ny;
+            const int exr = (int)(((float)i + 0.5f) * rny), ey = i - exr * ny, ex = ex0 + exr;
             const double g = blx[ex].gap2 + bly[ey].gap2;
             if (g <= R2c) {
                 const double rem = R2c - g;
@@ -1633,9 +1636,18 @@ __device__ __forceinline__ void wave_reduce_emit(const T *acc, double *red, Emit
     }
 }
 
+// Block rows held in LDS at once: all emax^2 of the widest box up to
+// kRowCap; wider boxes are traversed in slices of whole x entries (at least
+// one: ny <= emax rows).
+constexpr int kRowCap = 1024;
+__host__ __device__ constexpr int row_capacity(int emax)
+{
+    return emax * emax <= kRowCap ? emax * emax : (kRowCap > emax ? kRowCap : emax);
+}
+
 // LDS layout of the pair-major kernels: the x and y point tables
 // txy[2][4 emax], the z point table tz[4 emax], then the block lists
-// bl[3][emax], their counts and the block rows (at most emax^2).
+// bl[3][emax], their counts and the block rows (row_capacity(emax)).
 template <typename T>
 struct PairSmem {
     static __host__ __device__ size_t table_bytes(int emax)
@@ -1655,11 +1667,31 @@ struct PairSmem {
     static size_t bytes(int emax, bool tri = false)
     {
         const size_t off = table_bytes(emax);
-        const size_t b = off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)emax * emax;
+        const size_t b =
+            off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)row_capacity(emax);
         const size_t red = tri ? kRedBytesTri : kRedBytes;
         return b > red ? b : red;   // the area is reused for the final reduction
     }
 };
+
+// The pair image's blocks, row by row, in slices of whole x entries that fit
+// the LDS rows (one slice unless the box is wider than kRowCap rows); the
+// visitor's state carries over from slice to slice.  Ends with a barrier.
+template <typename T, typename Vis>
+__device__ __forceinline__ void traverse_slices(const PairRec &r, const PairSeg &sg, const PtXY<T> *txy,
+                                                const PtZ<T> *tz, const AxisBlock *bl, const int *cnt,
+                                                BlockRow *rows, Vis &vis)
+{
+    const int nx = uni(cnt[0]), ny = uni(cnt[1]);
+    const int xs = ny > 0 ? (sg.row_cap / ny > 1 ? sg.row_cap / ny : 1) : nx;
+    for (int ex0 = 0; ex0 < nx; ex0 += xs) {
+        const int nrows = build_rows(r.R2 * kCullSlack, sg.G, sg.vz, bl, sg.emax, cnt, rows, ex0,
+                                     ex0 + xs < nx ? ex0 + xs : nx);
+        __syncthreads();
+        for_each_point<T>(txy, tz, sg.emax, rows, nrows, sg.Vb, vis);
+        __syncthreads();   // the rows are rebuilt for the next slice
+    }
+}
 
 // Moments of degree LT of one pair image (pair-major traversal), wave-summed
 // into LDS past the reduction area; returns their address.  A general cell
@@ -1678,12 +1710,10 @@ __device__ __forceinline__ const double *pair_moments(const PairSeg &sg, const P
     PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
     pair_setup<true, T, TRI>(r, G, txy, tz, bl, emax, cnt);
     __syncthreads();
-    const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
-    __syncthreads();
     using Vis = std::conditional_t<TRI, TensorVisitTri<LT, T>, TensorVisit<LT, T>>;
     Vis vis(r, G);
-    for_each_point<T>(txy, tz, emax, rows, nrows, sg.Vb, vis);
-    __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+    traverse_slices<T>(r, sg, txy, tz, bl, cnt, rows, vis);
+    // the traversal's LDS reads are done; the area becomes red[8][65]
     double *red = reinterpret_cast<double *>(smem_raw);
     double *mom = red + 8 * 65;
     wave_reduce_emit<ntab(LT), T>(vis.Vm, red, [&](int k, double v) { mom[k] = v; });
@@ -1753,8 +1783,6 @@ k_mat(SegTable<PairSeg> tab)
         PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
         pair_setup<false, T>(r, G, txy, tz, bl, emax, cnt);
         __syncthreads();
-        const int nrows = build_rows(r.R2 * kCullSlack, G, sg.vz, bl, emax, cnt, rows);
-        __syncthreads();
         T acc[NA * NB];
 #pragma unroll
         for (int i = 0; i < NA * NB; ++i) acc[i] = T(0);
@@ -1770,8 +1798,8 @@ k_mat(SegTable<PairSeg> tab)
             }
         };
         DirectVisit<T, decltype(body)> vis(body, r);
-        for_each_point<T>(txy, tz, emax, rows, nrows, sg.Vb, vis);
-        __syncthreads();   // the traversal's LDS reads are done; the area becomes red[8][65]
+        traverse_slices<T>(r, sg, txy, tz, bl, cnt, rows, vis);
+        // the traversal's LDS reads are done; the area becomes red[8][65]
         wave_reduce_emit<NA * NB, T>(acc, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
             const int i = k / NB, j = k - (k / NB) * NB;
             atomicAdd(&sg.out[(long long)(r.ao_a + i) * n_ao + r.ao_b + j], scale * v);

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import log, to_dev, to_np
+from gpu_helpers import log, rel_err, to_dev, to_np
 from paper_2603_24881_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -105,18 +105,45 @@ def test_everything_screened_out_gives_zeros():
     g.close()
 
 
-def test_too_wide_sphere_is_rejected_with_a_message():
-    """A very diffuse function on a very fine single mesh: its truncation
-    sphere's point tables would not fit a workgroup's LDS; the plan call fails
-    with GPW_EUNSUPPORTED and says why instead of failing at launch."""
-    from paper_2603_24881_amd import _lib
+def _diffuse_system(name, L, mesh, exps, ls, tau):
+    n = len(ls)
+    return synth.System(name=name, cell=np.array([L, L, L]), coords=np.array([[0.45 * L, 0.5 * L, 0.55 * L]]),
+                        shell_atom=np.zeros(n, dtype=np.int32), shell_l=np.array(ls, dtype=np.int32),
+                        shell_nprim=np.ones(n, dtype=np.int32), shell_prim0=np.arange(n, dtype=np.int32),
+                        exps=np.array(exps), coefs=np.ones(n), ke_cutoff_ry=[],
+                        mesh=np.array([mesh], dtype=np.int32), tau=tau, n_occ=1)
+
+
+@pytest.mark.parametrize("case", ["sliced", "very_wide"])
+def test_wide_spheres_are_traversed_in_slices(case):
+    """Diffuse functions on fine single meshes: the pair boxes hold more block
+    rows than the LDS does, so the pair-major kernels walk them in slices of
+    x entries.  rho, the matrix and the gradient against the oracle."""
+    import torch
     from paper_2603_24881_amd.gpw import GPW
-    s = synth.System(name="wide", cell=np.array([40.0, 40.0, 40.0]), coords=np.array([[20.0, 20.0, 20.0]]),
-                     shell_atom=np.array([0], dtype=np.int32), shell_l=np.array([0], dtype=np.int32),
-                     shell_nprim=np.array([1], dtype=np.int32), shell_prim0=np.array([0], dtype=np.int32),
-                     exps=np.array([0.02]), coefs=np.array([1.0]), ke_cutoff_ry=[],
-                     mesh=np.array([[600, 600, 600]], dtype=np.int32), tau=1e-6, n_occ=1)
-    with pytest.raises(_lib.GPWError) as ei:
-        GPW(s)
-    log(f"  {ei.value}")
-    assert ei.value.status == 2 and "LDS" in str(ei.value)   # GPW_EUNSUPPORTED
+    if case == "sliced":      # about 38 blocks per axis, 3 slices
+        s = _diffuse_system("sliced", 20.0, (128, 128, 128), [0.05, 0.07], [0, 1], 1e-6)
+    else:                     # about 112 blocks per axis, 13 slices
+        s = _diffuse_system("very_wide", 40.0, (480, 480, 480), [0.02], [0], 1e-6)
+    g = GPW(s)
+    emax = (g.info["max_box_width"] + 3) // 4
+    log(f"  {case}: max box width {g.info['max_box_width']} points")
+    assert emax * emax > 1024
+    o = oracle.Oracle(s)
+    D = synth.make_density(s)
+    V = synth.make_potentials(o.meshes, 5)
+    rho = g.rho(to_dev(D))
+    M = g.mat([to_dev(v) for v in V])
+    G = g.grad(to_dev(D), [to_dev(v) for v in V])
+    torch.cuda.synchronize()
+    e = rel_err(to_np(rho[0]), o.rho(D)[0])
+    log(f"  rho rel err {e:.2e}")
+    assert e < 1e-10
+    e = rel_err(to_np(M), o.mat(V))
+    log(f"  M rel err {e:.2e}")
+    assert e < 1e-10
+    go = o.grad(D, V)
+    e = float(np.abs(to_np(G) - go).max() / max(np.abs(go).max(), 1e-300))
+    log(f"  grad rel err {e:.2e} (max |ref| {np.abs(go).max():.2e})")
+    assert e < 1e-10 or np.abs(to_np(G) - go).max() < 1e-12
+    g.close()
