@@ -6,16 +6,25 @@ potentials -> matrix) of the 256-water-like system (config-5 member with 256
 water units: 768 atoms, 10496 Cartesian AOs, levels 400/130/45/15 Ry, mesh
 192^3/108^3/64^3/40^3, tau = 1e-6), FP64, inputs resident in HBM.
 
-Prints ONE JSON line.  ``value`` is GFLOP/s of the arithmetic the rho and mat
-kernels perform (the plan's kernel flop model: the direct evaluation for the
-classes evaluated directly, the coefficient-tensor Horner evaluation of Eq.
-(rho1) and the potential moments for the others), so it and ``roofline.frac``
-measure work done.  ``convention_gflops`` counts instead the fixed
-per-(pair image, grid point) convention F = 2 n_a n_b + 2 (n_a + n_b) + 4 of
-the direct evaluation over the 64 points of every 4x4x4 block a truncation
+Prints ONE JSON line.  ``value`` is GFLOP/s of the FP64 arithmetic the rho
+and mat kernels execute: (2 FMA + ADD + MUL) x 64 lanes per evaluation from
+the rocprofv3 FP64 VALU counters in profiles/ while the kernel sources still
+hash to the value recorded there, else the plan's kernel flop model (the
+direct evaluation for the classes evaluated directly, the coefficient-tensor
+Horner evaluation of Eq. (rho1) and the potential moments for the others).
+``roofline`` prices the slower of eval_rho and eval_mat (all its launches, timed
+with events on the stream they run on) against the FP64 vector peak, with its
+HBM bytes from the counter summary.  ``convention_gflops`` counts instead the
+fixed per-(pair image, grid point) convention F = 2 n_a n_b + 2 (n_a + n_b) + 4
+of the direct evaluation over the 64 points of every 4x4x4 block a truncation
 sphere meets; the factorised kernels need fewer operations than that, so the
 convention rate of a class can exceed the hardware peak.  ``useful_gflops``
-counts the convention over the points inside the spheres only.
+counts the convention over the points inside the spheres only.  The serving
+block replays a Poisson trace of mixed requests at several rates, continuous
+batching against one request at a time; ``cpu_baseline`` times the oracle on
+a bounded sample of the same workload on the host.
+
+``--summarize DIR`` writes the profiles/ summaries from rocprofv3 outputs.
 """
 from __future__ import annotations
 
@@ -52,6 +61,9 @@ def parse():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM byte counters) and exit")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write the profiles/ summaries from the rocprofv3 outputs under DIR (no GPU; see "
+                         "summarize_profiles) and exit")
     return ap.parse_args()
 
 
@@ -259,8 +271,277 @@ def serving(n, rates, budget_gb):
     return out
 
 
+# ---------------------------------------------------------------- profile summaries
+#
+# The rocprofv3 runs behind profiles/ (each its own process, from /tmp with
+# TMPDIR=/tmp, <repo> the repository root, <out> = DIR/<name>):
+#   stats:     rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- python3 <repo>/bench.py
+#                --steps 3 --warmup 1 --extras 0 --serve-requests 0 --no-cpu-baseline   (stderr to DIR/bench.err)
+#   stats_x:   the same without --extras 0 (gradient and meta-GGA terms)
+#   f64:       rocprofv3 --pmc SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64
+#                SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE --output-format csv
+#                -d <out> -o run -- python3 <repo>/bench.py --steps 1 --warmup 0 --extras 0 --serve-requests 0
+#                --no-cpu-baseline
+#   fetch, write: rocprofv3 --pmc FETCH_SIZE (WRITE_SIZE) ... the stats command's bench.py arguments
+#   cal_fetch, cal_write: the same two counters on python3 <repo>/bench.py --calibrate-copy
+#   sq1:       rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES ... (stats arguments)
+#   sq2:       rocprofv3 --pmc SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_BUSY_CU_CYCLES ... (stats arguments)
+
+CLASS_NAMES = ["ss", "ps", "pp", "ds", "dp", "dd", "fs", "fp", "fd", "ff", "gs", "gp", "gd", "gf", "gg"]
+
+
+def _rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name):
+    import re
+    n = re.sub(r"\(.*", "", name).replace("void ", "")
+    return n if len(n) <= 60 else n[:40] + "... (library GEMM)" if n.startswith("Cijk") else n[:57] + "..."
+
+
+def _class_kernel(name):
+    """(operation, class index) of an FP64 class kernel, else None."""
+    import re
+    m = re.match(r"gpw::k_(rho2?|mat|grad|tau|mat_tau|grad_tau)<(\d), (\d)[,>]", name)
+    if not m or "double" not in name or "true>" in name:
+        return None
+    la, lb = int(m.group(2)), int(m.group(3))
+    op = {"rho2": "rho"}.get(m.group(1), m.group(1))
+    return op, la * (la + 1) // 2 + lb
+
+
+def _counters(path):
+    """Per kernel: counter sums over its dispatches, the dispatch count and the
+    summed dispatch durations (ns)."""
+    import collections
+    disp, meta = collections.defaultdict(dict), {}
+    for r in _rows(path):
+        d = int(r["Dispatch_Id"])
+        disp[d][r["Counter_Name"]] = disp[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        meta[d] = (_short(r["Kernel_Name"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for d, c in disp.items():
+        k, dur = meta[d]
+        per[k]["_n"] += 1
+        per[k]["_ns"] += dur
+        for n, v in c.items():
+            per[k][n] += v
+    return per
+
+
+def _trace(path):
+    import collections
+    tr = collections.defaultdict(list)
+    for r in _rows(path):
+        tr[_short(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return tr
+
+
+def _flop_model(op, c, inc):
+    """The plan's kernel flop model of one class (per evaluation), as in the partitioner."""
+    la = next(l for l in range(5) if (l + 1) * (l + 2) // 2 > c)
+    lb = c - la * (la + 1) // 2
+    L = la + lb
+    na, nb = (la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2
+    f1 = 2 * na * nb + 2 * (na + nb) + 4
+    tensor_rho = la == 2 or (la == 3 and 1 <= lb <= 2) or (la == 4 and lb >= 1)
+    ft = 8 * (L + 2) * (L + 1) * L / 6 + 32 * (L + 1) * L / 2 + 16 + 64 * (2 * L + 3)
+    if op == "rho":
+        return (ft if tensor_rho else 64 * f1) * inc, 64 * f1 * inc
+    return 64 * ((2 * L + 3) if L >= 2 else f1) * inc, 64 * f1 * inc
+
+
+def summarize_profiles(d):
+    """Write profiles/*water256* from the rocprofv3 outputs under d (layout above)."""
+    import re
+    import statistics
+    prof = os.path.join(ROOT, "profiles")
+    inc = None
+    for line in open(os.path.join(d, "bench.err")):
+        if "[bench] per class:" in line:
+            inc = [int(x) for x in re.findall(r"/ (\d+) blocks", line)]
+    assert inc and len(inc) == 15, "bench.err lacks the per-class line"
+    sha = _sources_sha()
+    stats = _rows(os.path.join(d, "stats", "run_kernel_stats.csv"))
+    tr = _trace(os.path.join(d, "stats", "run_kernel_trace.csv"))
+    NEV = 6     # evaluations of eval_rho and of eval_mat in the stats command
+    hdr = ("Command (from the repository root on one MI355X, `<repo>` its absolute path; `cd /tmp && export "
+           "TMPDIR=/tmp` first):\n\n```\n")
+    cmd_stats = ("rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- python3 <repo>/bench.py "
+                 "--steps 3 --warmup 1 --extras 0 --serve-requests 0 --no-cpu-baseline")
+    # ---- kernel stats of eval_rho / eval_mat
+    lines, tot = [], {"rho": 0.0, "mat": 0.0}
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        k = _short(r["Name"])
+        ck = _class_kernel(k)
+        calls, total = int(r["Calls"]), float(r["TotalDurationNs"]) * 1e-6
+        extra = ""
+        if ck and ck[0] in ("rho", "mat"):
+            model, conv = _flop_model(ck[0], ck[1], inc[ck[1]])
+            t = total / NEV * 1e-3
+            tot[ck[0]] += t
+            extra = (f" {CLASS_NAMES[ck[1]]} | {inc[ck[1]]} | {t * 1e3:.3f} | {conv / t / 1e12:.2f} | "
+                     f"{model / t / 1e12:.2f} | {model / t / PEAK_FP64:.3f} |")
+        else:
+            extra = " | | | | | |"
+        if total < 0.05 and not ck:
+            continue
+        lines.append(f"| `{k}` | {calls} | {total:.3f} | {float(r['AverageNs']) * 1e-3:.1f} |{extra}")
+    txt = ("# Kernel times of eval_rho / eval_mat, 256-water-like system (768 atoms, 10496 AOs, 4 levels, "
+           "tau 1e-6), FP64\n\n" + hdr + cmd_stats + "\n```\n\n"
+           f"`rocprofv3 --kernel-trace --stats` totals (`run_kernel_stats.csv`); the run evaluates eval_rho and "
+           f"eval_mat {NEV} times each (1 warm-up + 3 steps + 2 + 2 timed single-op repeats), one launch per "
+           "(operation, class) per evaluation.  conv = the counting convention F = 2 n_a n_b + 2 (n_a + n_b) + 4 "
+           "per point of every visited 4^3 block; model = the plan's kernel flop model (the arithmetic of the "
+           "form each class uses); frac = model rate / 78.6 TFLOP/s.\n\n"
+           "| kernel | calls | total ms | avg us | class | incidences | ms / eval | conv TF/s | model TF/s | "
+           "model frac |\n|---|---:|---:|---:|---|---:|---:|---:|---:|---:|\n" + "\n".join(lines) +
+           f"\n\nPer evaluation, class kernels only: eval_rho {tot['rho'] * 1e3:.3f} ms, eval_mat "
+           f"{tot['mat'] * 1e3:.3f} ms (bench.py's `ms_rho` / `ms_mat` add the packing, fills and block copies).\n"
+           f"\nsource_sha256 {sha}\n")
+    open(os.path.join(prof, "k_rho_k_mat_water256_kernel_stats.md"), "w").write(txt)
+    # ---- gradient and meta-GGA kernels (the 256-water launches: the longest of each)
+    trx = _trace(os.path.join(d, "stats_x", "run_kernel_trace.csv"))
+    lines, tot2 = [], {}
+    for k in sorted(trx):
+        ck = _class_kernel(k)
+        if not ck or ck[0] not in ("grad", "tau", "mat_tau", "grad_tau"):
+            continue
+        durs = sorted(trx[k])[-3:]
+        t = statistics.median(durs) * 1e-6
+        tot2[ck[0]] = tot2.get(ck[0], 0.0) + t
+        lines.append(f"| `{k}` | {ck[0]} | {CLASS_NAMES[ck[1]]} | {len(trx[k])} | {t:.3f} |")
+    txt = ("# Kernel times of eval_grad and the meta-GGA terms, 256-water-like system, FP64\n\n" + hdr +
+           cmd_stats.replace(" --extras 0", "") + "\n```\n\n"
+           "From `run_kernel_trace.csv`: the 256-water gradient and meta-GGA terms are evaluated 3 times each; "
+           "the FP32 error report also evaluates the smaller diamond system with the FP64 kernels (shorter "
+           "launches), so each row is the median of the 3 longest launches.\n\n"
+           "| kernel | operation | class | launches | ms / eval |\n|---|---|---|---:|---:|\n" + "\n".join(lines) +
+           "\n\nPer evaluation: " + ", ".join(f"{op} {t:.3f} ms" for op, t in sorted(tot2.items())) +
+           f"\n\nsource_sha256 {sha}\n")
+    open(os.path.join(prof, "k_grad_k_tau_water256_kernel_stats.md"), "w").write(txt)
+    # ---- FP64 counters
+    per = _counters(os.path.join(d, "f64", "run_counter_collection.csv"))
+    lines, tot = [], {"rho": [0.0, 0.0, 0.0], "mat": [0.0, 0.0, 0.0]}
+    for k in sorted(per, key=lambda k: (_class_kernel(k) or ("z", 0))):
+        ck = _class_kernel(k)
+        if not ck or ck[0] not in ("rho", "mat"):
+            continue
+        op, c = ck
+        p = per[k]
+        n = p["_n"]
+        model, conv = _flop_model(op, c, inc[c])
+        cnt = (2 * p["SQ_INSTS_VALU_FMA_F64"] + p["SQ_INSTS_VALU_ADD_F64"] + p["SQ_INSTS_VALU_MUL_F64"]) * 64 / n
+        t = statistics.median(sorted(tr[k])) * 1e-9
+        clk = p["GRBM_GUI_ACTIVE"] / 8 / (p["_ns"] * 1e-9) / 1e9
+        valu = p["SQ_INSTS_VALU"] / n
+        tot[op][0] += t
+        tot[op][1] += model
+        tot[op][2] += cnt
+        lines.append(f"| `{k}` | {CLASS_NAMES[c]} | {inc[c]} | {t * 1e3:.3f} | {conv / t / 1e12:.2f} | "
+                     f"{model / t / 1e12:.2f} | {model / t / PEAK_FP64:.3f} | {cnt / t / 1e12:.2f} | "
+                     f"**{cnt / t / PEAK_FP64:.3f}** | {cnt / model:.2f} | {valu / (256 * t * 2.4e9):.2f} | {clk:.2f} |")
+    txt = ("# FP64 work of k_rho / k_mat per (l_a, l_b) class, 256-water-like system (768 atoms, 10496 AOs, 4 "
+           "levels, tau 1e-6), FP64\n\nCommands (from the repository root on one MI355X, `<repo>` its absolute "
+           "path; `cd /tmp && export TMPDIR=/tmp` first), each in its own run:\n\n```\n"
+           "rocprofv3 --pmc SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_TRANS_F64 "
+           "SQ_INSTS_VALU SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE --output-format csv -d <out> -o run -- python3 "
+           "<repo>/bench.py --steps 1 --warmup 0 --extras 0 --serve-requests 0 --no-cpu-baseline\n" + cmd_stats +
+           "\n```\n\nThe counter run evaluates eval_rho and eval_mat 3 times each; counts below are per "
+           "evaluation.  Durations: median launch of each kernel in the kernel-trace run (no counters attached).\n"
+           "* conv: the counting convention F = 2 n_a n_b + 2 (n_a + n_b) + 4 per point of every visited 4^3 block "
+           "(the direct evaluation; the factorised classes do less, so it can exceed the peak).\n"
+           "* model: the plan's kernel flop model (`flops_rho_exec`, `flops_mat_exec`).\n"
+           "* counters: (2 FMA_F64 + ADD_F64 + MUL_F64) x 64 lanes, the FP64 arithmetic the kernel executes (exp "
+           "and address arithmetic in FP64 included; TRANS_F64 is 0: FP64 exp is FMA code).\n"
+           "* frac = rate / 78.6 TFLOP/s (MI355X FP64 vector peak at 2.4 GHz); VALU/CU-cyc = SQ_INSTS_VALU wave "
+           "instructions per CU and 2.4 GHz cycle of the kernel's duration (one FP64 VALU instruction per CU-cycle "
+           "at most); clock = GRBM_GUI_ACTIVE / 8 XCDs / duration in the counter run (GHz).\n\n"
+           "| kernel | class | incidences | ms / eval | conv TF/s | model TF/s | model frac | counter TF/s | "
+           "counter frac | counter/model | VALU/CU-cyc | clock |\n"
+           "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|\n" + "\n".join(lines) +
+           f"\n\nPer evaluation: eval_rho kernels {tot['rho'][0] * 1e3:.3f} ms, model {tot['rho'][1]:.4e} flops "
+           f"({tot['rho'][1] / tot['rho'][0] / PEAK_FP64:.3f} of peak), counters {tot['rho'][2]:.4e} flops "
+           f"({tot['rho'][2] / tot['rho'][0] / PEAK_FP64:.3f} of peak); eval_mat kernels {tot['mat'][0] * 1e3:.3f} "
+           f"ms, model {tot['mat'][1]:.4e} ({tot['mat'][1] / tot['mat'][0] / PEAK_FP64:.3f}), counters "
+           f"{tot['mat'][2]:.4e} ({tot['mat'][2] / tot['mat'][0] / PEAK_FP64:.3f}).\n\n"
+           "bench.py reads the two lines below (FP64 flops per evaluation from the counters) while the kernel "
+           "sources hash to `source_sha256`, and reports `value` and `roofline` from them; otherwise it falls back "
+           "to the plan's model.\n\n```\n"
+           f"eval_rho_flops {tot['rho'][2]:.6e}\neval_mat_flops {tot['mat'][2]:.6e}\nsource_sha256 {sha}\n```\n")
+    open(os.path.join(prof, "k_rho_k_mat_water256_fp64_counters.md"), "w").write(txt)
+    # ---- HBM traffic
+    def counter_sum(sub, name):
+        per = _counters(os.path.join(d, sub, "run_counter_collection.csv"))
+        return {k: p[name] for k, p in per.items()}
+    cf, cw = counter_sum("cal_fetch", "FETCH_SIZE"), counter_sum("cal_write", "WRITE_SIZE")
+    copy = max(cf, key=cf.get)      # the copy kernel (the fill before it reads nothing)
+    moved = 1 << 20     # KiB: one 1 GiB copy
+    sf, sw = moved / cf[copy], moved / cw[copy]
+    fe, wr = counter_sum("fetch", "FETCH_SIZE"), counter_sum("write", "WRITE_SIZE")
+    ops = {"eval_rho": lambda k: re.match(r"gpw::k_(rho2?<|pack_)", k) is not None,
+           "eval_mat": lambda k: re.match(r"gpw::k_(mat<|block_grid)", k) is not None}
+    out = [f"# HBM traffic of eval_rho and eval_mat, 256-water-like system, FP64",
+           "#", "# Commands (from the repository root on one MI355X, <repo> its absolute path; cd /tmp && export "
+           "TMPDIR=/tmp first), each its own run:",
+           "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out> -o run -- python3 <repo>/bench.py --steps 3 "
+           "--warmup 1 --extras 0 --serve-requests 0 --no-cpu-baseline",
+           "#   rocprofv3 --pmc WRITE_SIZE (the same)",
+           "#   calibration: the same two counters on `python3 <repo>/bench.py --calibrate-copy` (one 1 GiB "
+           "device-to-device copy)",
+           f"#   copy ({copy}): FETCH_SIZE {cf[copy]:.0f} KiB, WRITE_SIZE {cw[copy]:.0f} KiB for {moved} KiB "
+           f"moved -> scale FETCH by {sf:.4f}, WRITE by {sw:.4f}",
+           f"# Per evaluation = counter sums over the operation's kernels / {NEV} evaluations, scaled, in bytes:",
+           "# eval_rho = the packing and density kernels, eval_mat = the block copies of the potentials and the",
+           "# integration kernels; the zero fills of the outputs (k_fill: the rho grids, 70 MB, and M, 0.88 GB,",
+           "# written per evaluation) are shared by both operations and left out.",
+           "# bench.py reports `traffic` only while the kernel sources hash to source_sha256.",
+           f"source_sha256 {sha}"]
+    for op, sel in ops.items():
+        f = sum(v for k, v in fe.items() if sel(k)) * sf * 1024 / NEV
+        w = sum(v for k, v in wr.items() if sel(k)) * sw * 1024 / NEV
+        out += [f"{op}_fetch_bytes {f:.0f}", f"{op}_write_bytes {w:.0f}", f"{op}_bytes {f + w:.0f}"]
+    out.append("# per kernel (GB per evaluation, fetch / write):")
+    for k in sorted(fe, key=lambda k: -fe[k]):
+        if fe[k] * sf * 1024 / NEV < 1e6:
+            continue
+        out.append(f"#   {k:45s} {fe[k] * sf * 1024 / NEV / 1e9:7.3f} / {wr.get(k, 0.0) * sw * 1024 / NEV / 1e9:7.3f}")
+    open(os.path.join(prof, "eval_rho_eval_mat_water256_hbm_traffic.txt"), "w").write("\n".join(out) + "\n")
+    # ---- SQ issue counters
+    p1 = _counters(os.path.join(d, "sq1", "run_counter_collection.csv"))
+    p2 = _counters(os.path.join(d, "sq2", "run_counter_collection.csv"))
+    lines = []
+    for k in sorted(p1, key=lambda k: -p1[k].get("SQ_INSTS_VALU", 0.0)):
+        ck = _class_kernel(k)
+        if not ck or ck[0] not in ("rho", "mat") or k not in p2:
+            continue
+        a, b = p1[k], p2[k]
+        v = a["SQ_INSTS_VALU"]
+        lines.append(f"| `{k}` | {v / a['_n']:.3g} | {v / b['SQ_BUSY_CU_CYCLES']:.2f} | "
+                     f"{a['SQ_INSTS_SALU'] / v:.2f} | {b['SQ_INSTS_LDS'] / v:.2f} | {b['SQ_INSTS_VMEM_RD'] / v:.3f} |")
+    txt = ("# SQ issue counters of the k_rho / k_mat kernels, 256-water-like system, FP64\n\nCommands (as for the "
+           "kernel stats, `cd /tmp && export TMPDIR=/tmp` first), each its own run:\n\n```\n"
+           "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES --output-format csv -d <out> "
+           "-o run -- python3 <repo>/bench.py --steps 3 --warmup 1 --extras 0 --serve-requests 0 --no-cpu-baseline\n"
+           "rocprofv3 --pmc SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_BUSY_CU_CYCLES --output-format csv -d <out> -o run -- "
+           "python3 <repo>/bench.py --steps 3 --warmup 1 --extras 0 --serve-requests 0 --no-cpu-baseline\n```\n\n"
+           "VALU per evaluation (wave64 instructions); VALU / CU-cycle = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES (at most 1 "
+           "for FP64: a wave64 FP64 instruction occupies one of the CU's 4 SIMDs for 4 cycles); SALU, LDS, VMEM per "
+           "VALU instruction.\n\n"
+           "| kernel | VALU / eval | VALU / CU-cycle | SALU / VALU | LDS / VALU | VMEM / VALU |\n"
+           "|---|---:|---:|---:|---:|---:|\n" + "\n".join(lines) + f"\n\nsource_sha256 {sha}\n")
+    open(os.path.join(prof, "k_rho_k_mat_water256_sq_counters.md"), "w").write(txt)
+    print("profiles written", file=sys.stderr)
+
+
 def main():
     args = parse()
+    if args.summarize:
+        summarize_profiles(args.summarize)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: --gpus above 1 is not supported (the path would shard by "
                                    "grid blocks, with one all-reduce of M per evaluation)"}))
