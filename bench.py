@@ -674,11 +674,21 @@ def main():
         log(f"[bench] meta-GGA: {out['meta_gga']}")
         del T
         g32 = GPW(system, precision="fp32")
-        g32.rho(D, out=rho)
-        g32.mat(V, out=M)
-        t32 = timed(lambda: (g32.rho(D, out=rho), g32.mat(V, out=M)), max(2, args.steps // 2), stream)
+        rho32 = g32.new_grids()
+        M32 = torch.empty_like(M)
+        g32.rho(D, out=rho32)
+        g32.mat(V, out=M32)
+        t32 = timed(lambda: (g32.rho(D, out=rho32), g32.mat(V, out=M32)), max(2, args.steps // 2), stream)
         out["ms_step_fp32"] = round(t32 * 1e3, 4)
-        log(f"[bench] fp32 step {t32 * 1e3:.2f} ms")
+        # the FP32 kernels against the FP64 ones on this system (rho per level, M)
+        g.rho(D, out=rho)
+        g.mat(V, out=M)
+        torch.cuda.synchronize()
+        out["fp32_vs_fp64_here"] = {
+            "rho_rel_err": max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(rho32, rho)),
+            "M_rel_err": float((M32 - M).abs().max() / M.abs().max())}
+        log(f"[bench] fp32 step {t32 * 1e3:.2f} ms, errors {out['fp32_vs_fp64_here']}")
+        del rho32, M32
         g32.close()
     if args.extras:
         out["fp32_error"] = fp32_errors()

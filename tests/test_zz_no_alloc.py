@@ -105,3 +105,25 @@ def test_scratch_beyond_the_fixed_array_is_rejected():
     assert ei.value.status == 5
     assert "scratch" in _lib.gpw_last_error()
     p.close()
+
+
+def test_noalloc_on_a_general_cell():
+    """The same entry point on a triclinic cell (the index-coordinate kernels)."""
+    import torch
+    import tiny
+    from paper_2603_24881_amd import _lib, synth
+    from paper_2603_24881_amd.gpw import GPW
+    log("[noalloc] triclinic cell")
+    cell = np.array([[7.0, 0.0, 0.0], [1.9, 7.6, 0.0], [-1.2, 1.4, 8.2]])
+    s = tiny.tiny_system(cell=cell, mesh=((18, 21, 23),), tau=1e-10)
+    g = GPW(s)
+    V = [to_dev(v) for v in synth.make_potentials(g.meshes, 7)]
+    ref = torch.empty((g.n_ao, g.n_ao), dtype=torch.float64, device=V[0].device)
+    out = torch.full_like(ref, float("nan"))
+    _lib.gpw_eval_mat(g.plan, V, ref)
+    _lib.gpw_eval_mat_noalloc(g.plan, V, out)
+    torch.cuda.synchronize()
+    e = rel_err(to_np(out), to_np(ref))
+    log(f"  M rel diff {e:.2e}")
+    assert not bool(torch.isnan(out).any()) and e < TOL
+    g.close()
