@@ -1,6 +1,6 @@
-"""gpw_eval_batch: tasks of several plans (sizes, classes, precisions) in one
-batched set of launches give the same results as the single calls, and the
-single calls still match the oracle."""
+"""gpw_eval_batch: tasks of several plans (sizes, classes, precisions,
+orthorhombic and general cells) in one batched set of launches give the same
+results as the single calls, and the single calls still match the oracle."""
 from __future__ import annotations
 
 import numpy as np
@@ -13,12 +13,17 @@ from paper_2603_24881_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 
+SKEW = np.array([[7.0, 0.0, 0.0], [1.9, 7.6, 0.0], [-1.2, 1.4, 8.2]])
+
 
 def _systems():
     return [("config1", synth.config1(), "fp64"),
             ("tiny-spdf", tiny.tiny_system(mesh=((18, 21, 23),), tau=1e-10), "fp64"),
             ("config2", synth.config2(), "fp64"),
-            ("tiny-spdf-fp32", tiny.tiny_system(mesh=((20, 24, 28),), tau=1e-10), "fp32")]
+            ("tiny-spdf-fp32", tiny.tiny_system(mesh=((20, 24, 28),), tau=1e-10), "fp32"),
+            # general cells: their segments take the index-coordinate kernels in the same launches
+            ("tiny-skew", tiny.tiny_system(cell=SKEW, mesh=((18, 21, 23),), tau=1e-10), "fp64"),
+            ("tiny-skew-fp32", tiny.tiny_system(cell=SKEW, mesh=((16, 18, 20),), tau=1e-10, seed=9), "fp32")]
 
 
 def test_batch_matches_single_calls():
