@@ -354,11 +354,12 @@ def _flop_model(op, c, inc):
     return 64 * ((2 * L + 3) if L >= 2 else f1) * inc, 64 * f1 * inc
 
 
-def summarize_profiles(d):
-    """Write profiles/*water256* from the rocprofv3 outputs under d (layout above)."""
+def summarize_profiles(d, prof=None):
+    """Write the *water256* summaries into prof (default profiles/) from the
+    rocprofv3 outputs under d (layout above)."""
     import re
     import statistics
-    prof = os.path.join(ROOT, "profiles")
+    prof = prof or os.path.join(ROOT, "profiles")
     inc = None
     for line in open(os.path.join(d, "bench.err")):
         if "[bench] per class:" in line:
