@@ -1727,6 +1727,142 @@ __device__ __forceinline__ const double *pair_moments(const PairSeg &sg, const P
     return mom;
 }
 
+// ------------------------------------ element formation from the moments
+//
+// Two forms.  Compile-time: element e of the pair image goes to lane e % 64
+// with every exponent and expansion term resolved at compile time, each
+// element under its own lane's mask (the wave steps through all of them).
+// Runtime: one lane per element (i, j) with the element's Cartesian exponents
+// as runtime values, every lane running the same instructions on products of
+// one-axis factors (polynomials in u = x - A_x) contracted with the moments.
+// Chosen per class by measurement on the 256-water system: the runtime form
+// for the classes with many elements, the compile-time one where its
+// specialised code is shorter.
+__host__ __device__ constexpr bool mat_runtime_form(int la, int lb) { return (la == 2 && lb == 2) || (la >= 3 && lb >= 1); }
+__host__ __device__ constexpr bool grad_runtime_form(int la, int lb)
+{
+    return (la == 1 && lb == 1) || (la == 2 && lb == 2) || (la >= 3 && lb >= 1);
+}
+
+// (d/du)^N (u^p e^{-a u^2}) / e^{-a u^2}, coefficients of u^k for k = 0..W-1
+// (two_a = 2a): u^p; p u^(p-1) - 2a u^(p+1); p(p-1) u^(p-2) - 2a(2p+1) u^p +
+// 4a^2 u^(p+2).
+template <int W, int N>
+__device__ __forceinline__ void deriv_poly(int p, double two_a, double *g)
+{
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        double v;
+        if constexpr (N == 0)
+            v = k == p ? 1.0 : 0.0;
+        else if constexpr (N == 1)
+            v = (k == p - 1 ? (double)p : 0.0) + (k == p + 1 ? -two_a : 0.0);
+        else
+            v = (k == p - 2 ? (double)(p * (p - 1)) : 0.0) + (k == p ? -two_a * (2 * p + 1) : 0.0) +
+                (k == p + 2 ? two_a * two_a : 0.0);
+        g[k] = v;
+    }
+}
+
+// One-axis factor of a term: [(d/du)^NA (u^p e^{-a u^2})] [(d/dv)^NB
+// (v^q e^{-b v^2})] divided by both exponentials, with v = u + c (c = A - B),
+// as a polynomial in u: f[k], k = 0..W-1 (W at least p + q + NA + NB + 1 for
+// the lane's p <= PM, q <= QM; higher entries are zero).
+template <int W, int PM, int QM, int NA, int NB>
+__device__ __forceinline__ void axis_factor(int p, int q, double two_a, double two_b, double c, double *f)
+{
+    constexpr int GW = PM + NA + 1, HW = QM + NB + 1;
+    static_assert(GW + HW - 1 <= W, "factor width");
+    double g[GW], h[HW], hu[HW];
+    deriv_poly<GW, NA>(p, two_a, g);
+    deriv_poly<HW, NB>(q, two_b, h);
+    // h(u + c) by Horner's rule in (u + c)
+#pragma unroll
+    for (int k = 0; k < HW; ++k) hu[k] = 0.0;
+    hu[0] = h[HW - 1];
+#pragma unroll
+    for (int m = HW - 2; m >= 0; --m) {
+#pragma unroll
+        for (int k = HW - 1 - m; k >= 1; --k) hu[k] = hu[k - 1] + c * hu[k];
+        hu[0] = c * hu[0] + h[m];
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) f[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < GW; ++i)
+#pragma unroll
+        for (int j = 0; j < HW; ++j) f[i + j] += g[i] * hu[j];
+}
+
+// sum over kx + ky + kz <= LT of fx[kx] fy[ky] fz[kz] mom[tidx(LT, kx, ky, kz)]
+template <int LT, int W>
+__device__ __forceinline__ double contract3(const double *fx, const double *fy, const double *fz, const double *mom)
+{
+    double sx = 0.0;
+#pragma unroll
+    for (int kx = 0; kx < W && kx <= LT; ++kx) {
+        double sy = 0.0;
+#pragma unroll
+        for (int ky = 0; ky < W && kx + ky <= LT; ++ky) {
+            double sz = 0.0;
+#pragma unroll
+            for (int kz = 0; kz < W && kx + ky + kz <= LT; ++kz) sz += fz[kz] * mom[tidx(LT, kx, ky, kz)];
+            sy += fy[ky] * sz;
+        }
+        sx += fx[kx] * sy;
+    }
+    return sx;
+}
+
+__device__ __forceinline__ void cart_exps(int l, int n, int *e)
+{
+    e[0] = cart_lx(l, n);
+    e[1] = cart_ly(l, n);
+    e[2] = l - e[0] - e[1];
+}
+
+// Matrix element (i, j) from the moments of degree l_a + l_b, runtime form:
+// per axis the factor u^a (u + c)^b with c = A - B (the binomial expansion of
+// Eq. (binomial)), contracted with the moments.
+template <int LA, int LB>
+__device__ __forceinline__ double mat_element_rt(int i, int j, const double *AB, const double *mom)
+{
+    constexpr int L = LA + LB, W = L + 1;
+    int a[3], b[3];
+    cart_exps(LA, i, a);
+    cart_exps(LB, j, b);
+    double f[3][W];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) axis_factor<W, LA, LB, 0, 0>(a[e], b[e], 0.0, 0.0, AB[e], f[e]);
+    return contract3<L, W>(f[0], f[1], f[2], mom);
+}
+
+// d/dA_f and d/dB_f of the element (i, j) from the moments of degree
+// l_a + l_b + 1, runtime form: with a_i depending on r - A, d/dA_f a_i =
+// -d_f a_i (the derivative in r, the Gaussian factor included), and likewise
+// for b_j; into g6[f] (A) and g6[3 + f] (B).
+template <int LA, int LB>
+__device__ __forceinline__ void grad_element_rt(int i, int j, double two_a, double two_b, const double *AB,
+                                                const double *mom, double *g6)
+{
+    constexpr int L1 = LA + LB + 1, W = L1 + 1;
+    int a[3], b[3];
+    cart_exps(LA, i, a);
+    cart_exps(LB, j, b);
+    double f0[3][W], fA[3][W], fB[3][W];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        axis_factor<W, LA, LB, 0, 0>(a[e], b[e], two_a, two_b, AB[e], f0[e]);
+        axis_factor<W, LA, LB, 1, 0>(a[e], b[e], two_a, two_b, AB[e], fA[e]);
+        axis_factor<W, LA, LB, 0, 1>(a[e], b[e], two_a, two_b, AB[e], fB[e]);
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        g6[f] = -contract3<L1, W>(f == 0 ? fA[0] : f0[0], f == 1 ? fA[1] : f0[1], f == 2 ? fA[2] : f0[2], mom);
+        g6[3 + f] = -contract3<L1, W>(f == 0 ? fB[0] : f0[0], f == 1 ? fB[1] : f0[1], f == 2 ? fB[2] : f0[2], mom);
+    }
+}
+
 // Matrix element (I, J) of a pair image from its potential moments:
 // sum over the binomial expansion of (x-B)^b around A (Eq. (binomial)) of
 // binom * (A-B)^(b-k) * moment(a + k); ab[d][p] = (A_d - B_d)^p.
@@ -1821,7 +1957,15 @@ k_mat(SegTable<PairSeg> tab)
         }
         constexpr int NE = NA * NB, NS = (NE + 63) / 64;
         double m[NS];
-        mat_elements<LA, LB>(std::make_integer_sequence<int, NE>{}, mom, ab, (int)threadIdx.x, m);
+        if constexpr (mat_runtime_form(LA, LB)) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int ij = q * 64 + (int)threadIdx.x;
+                m[q] = ij < NE ? mat_element_rt<LA, LB>(ij / NB, ij % NB, AB, mom) : 0.0;
+            }
+        } else {
+            mat_elements<LA, LB>(std::make_integer_sequence<int, NE>{}, mom, ab, (int)threadIdx.x, m);
+        }
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             const int ij = q * 64 + (int)threadIdx.x;
@@ -1926,8 +2070,22 @@ k_grad(SegTable<PairSeg> tab)
         for (int k = 1; k <= LB; ++k) ab[d][k] = ab[d][k - 1] * AB[d];
     }
     double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    grad_elements<LA, LB, T>(std::make_integer_sequence<int, NA * NB>{}, mom, ab, 2.0 * r.aa, 2.0 * r.ab, AB, Dp,
-                             n_ao, (int)threadIdx.x, g6);
+    if constexpr (grad_runtime_form(LA, LB)) {
+#pragma unroll 1
+        for (int e0 = 0; e0 < NA * NB; e0 += 64) {
+            const int e = e0 + (int)threadIdx.x;
+            if (e < NA * NB) {
+                double t6[6];
+                grad_element_rt<LA, LB>(e / NB, e % NB, 2.0 * r.aa, 2.0 * r.ab, AB, mom, t6);
+                const double dij = (double)Dp[(long long)(e / NB) * n_ao + e % NB];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) g6[k] += dij * t6[k];
+            }
+        }
+    } else {
+        grad_elements<LA, LB, T>(std::make_integer_sequence<int, NA * NB>{}, mom, ab, 2.0 * r.aa, 2.0 * r.ab, AB,
+                                 Dp, n_ao, (int)threadIdx.x, g6);
+    }
     const double scale = G.w * r.Kw;
     __syncthreads();   // every read of the moments is done
     wave_reduce_emit<6, double>(g6, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
@@ -1938,88 +2096,8 @@ k_grad(SegTable<PairSeg> tab)
 // ---------------------------------- kinetic-energy-density integration and gradient
 //
 // Matrix elements and gradients of the meta-GGA term from potential moments of
-// degree l_a + l_b + 2 (integration) and l_a + l_b + 3 (gradient).  One lane
-// per element (i, j): the element's Cartesian exponents are runtime values, so
-// every lane runs the same instructions and the elements of a pair image are
-// formed in parallel.  Each term is a product of one-axis factors, polynomials
-// in u = x - A_x, contracted with the moments.
-
-// (d/du)^N (u^p e^{-a u^2}) / e^{-a u^2}, coefficients of u^k for k = 0..W-1
-// (two_a = 2a): u^p; p u^(p-1) - 2a u^(p+1); p(p-1) u^(p-2) - 2a(2p+1) u^p +
-// 4a^2 u^(p+2).
-template <int W, int N>
-__device__ __forceinline__ void deriv_poly(int p, double two_a, double *g)
-{
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        double v;
-        if constexpr (N == 0)
-            v = k == p ? 1.0 : 0.0;
-        else if constexpr (N == 1)
-            v = (k == p - 1 ? (double)p : 0.0) + (k == p + 1 ? -two_a : 0.0);
-        else
-            v = (k == p - 2 ? (double)(p * (p - 1)) : 0.0) + (k == p ? -two_a * (2 * p + 1) : 0.0) +
-                (k == p + 2 ? two_a * two_a : 0.0);
-        g[k] = v;
-    }
-}
-
-// One-axis factor of a term: [(d/du)^NA (u^p e^{-a u^2})] [(d/dv)^NB
-// (v^q e^{-b v^2})] divided by both exponentials, with v = u + c (c = A - B),
-// as a polynomial in u: f[k], k = 0..W-1 (W at least p + q + NA + NB + 1 for
-// the lane's p <= PM, q <= QM; higher entries are zero).
-template <int W, int PM, int QM, int NA, int NB>
-__device__ __forceinline__ void axis_factor(int p, int q, double two_a, double two_b, double c, double *f)
-{
-    constexpr int GW = PM + NA + 1, HW = QM + NB + 1;
-    static_assert(GW + HW - 1 <= W, "factor width");
-    double g[GW], h[HW], hu[HW];
-    deriv_poly<GW, NA>(p, two_a, g);
-    deriv_poly<HW, NB>(q, two_b, h);
-    // h(u + c) by Horner's rule in (u + c)
-#pragma unroll
-    for (int k = 0; k < HW; ++k) hu[k] = 0.0;
-    hu[0] = h[HW - 1];
-#pragma unroll
-    for (int m = HW - 2; m >= 0; --m) {
-#pragma unroll
-        for (int k = HW - 1 - m; k >= 1; --k) hu[k] = hu[k - 1] + c * hu[k];
-        hu[0] = c * hu[0] + h[m];
-    }
-#pragma unroll
-    for (int k = 0; k < W; ++k) f[k] = 0.0;
-#pragma unroll
-    for (int i = 0; i < GW; ++i)
-#pragma unroll
-        for (int j = 0; j < HW; ++j) f[i + j] += g[i] * hu[j];
-}
-
-// sum over kx + ky + kz <= LT of fx[kx] fy[ky] fz[kz] mom[tidx(LT, kx, ky, kz)]
-template <int LT, int W>
-__device__ __forceinline__ double contract3(const double *fx, const double *fy, const double *fz, const double *mom)
-{
-    double sx = 0.0;
-#pragma unroll
-    for (int kx = 0; kx < W && kx <= LT; ++kx) {
-        double sy = 0.0;
-#pragma unroll
-        for (int ky = 0; ky < W && kx + ky <= LT; ++ky) {
-            double sz = 0.0;
-#pragma unroll
-            for (int kz = 0; kz < W && kx + ky + kz <= LT; ++kz) sz += fz[kz] * mom[tidx(LT, kx, ky, kz)];
-            sy += fy[ky] * sz;
-        }
-        sx += fx[kx] * sy;
-    }
-    return sx;
-}
-
-__device__ __forceinline__ void cart_exps(int l, int n, int *e)
-{
-    e[0] = cart_lx(l, n);
-    e[1] = cart_ly(l, n);
-    e[2] = l - e[0] - e[1];
-}
+// degree l_a + l_b + 2 (integration) and l_a + l_b + 3 (gradient), in the
+// runtime form for every class.
 
 // sum_d of the d_d a_i d_d b_j moments (moments of degree l_a + l_b + 2).
 template <int LA, int LB>
