@@ -248,10 +248,13 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                     r.rho = t.rho[l];
                     r.p0 = (int)pl->group_off[g];
                     r.G = pl->geom[l];
+                    int chunk = 0;   // the longest XCD range sets the segment's workgroups
+                    for (int x = 0; x < 9; ++x) r.xs[x] = pl->xsplit[g][x];
+                    for (int x = 0; x < 8; ++x) chunk = std::max(chunk, r.xs[x + 1] - r.xs[x]);
                     if (pl->tri)
-                        (tau ? cl.taus_t : cl.rhos_t).add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
+                        (tau ? cl.taus_t : cl.rhos_t).add(r, 8LL * chunk);
                     else
-                        (tau ? cl.taus : cl.rhos).add(r, pl->blk_off[g + 1] - pl->blk_off[g]);
+                        (tau ? cl.taus : cl.rhos).add(r, 8LL * chunk);
                 } else {
                     PairSeg q;
                     q.item0 = 0;

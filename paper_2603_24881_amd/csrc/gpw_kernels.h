@@ -94,6 +94,7 @@ struct RhoSeg {
     const void *Dpk;             // packed D sub-blocks of the group
     double *rho;                 // level grid
     int p0;                      // plan index of the group's first pair image
+    int xs[9];                   // items of the eight XCDs (xcd_ranged), balanced by work
     LevelGeom G;
 };
 // Blocks of slack past the end of a block copy: the pair-major traversal
@@ -871,8 +872,8 @@ __device__ __forceinline__ void rho_blocks(const SegTable<RhoSeg> &tab)
     double(*red)[65] = reinterpret_cast<double(*)[65]>(lds);
     const int lane = threadIdx.x;
     const RhoSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
-    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
-    if (item >= sg.count) return;
+    const long long item = xcd_ranged(blockIdx.x - sg.item0, sg.xs);
+    if (item < 0) return;
     const LevelGeom &G = sg.G;
     const int2 *__restrict__ inc = sg.inc;
     const T *__restrict__ Dpk = (const T *)sg.Dpk;
@@ -1008,8 +1009,8 @@ k_rho2(SegTable<RhoSeg> tab)
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const RhoSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
-    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
-    if (item >= sg.count) return;
+    const long long item = xcd_ranged(blockIdx.x - sg.item0, sg.xs);
+    if (item < 0) return;
     const LevelGeom &G = sg.G;
     const int2 *__restrict__ inc = sg.inc;
     const T *__restrict__ Dpk = (const T *)sg.Dpk;

@@ -645,6 +645,34 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     pl->max_axis_blocks = maxwb[1];
     for (int g = 0; g <= kMaxGroups; ++g) pl->blk_off[g] = flag_at[g];
     if (errf & 1) { err = "partitioner count and fill passes disagree"; return hipErrorUnknown; }
+    {
+        // deal each group's nonempty blocks to the eight XCDs in contiguous
+        // ranges of about equal work (list length plus a fixed per-block share
+        // for the reduction and the write): equal block counts would leave the
+        // XCDs with the sparser regions idle while the denser ones finish
+        std::vector<unsigned> hcnt((size_t)ncnt);
+        std::vector<int> hblk((size_t)nblk_total);
+        if (ncnt > 0) PCHK(hipMemcpyAsync(hcnt.data(), d_cnt, sizeof(unsigned) * (size_t)ncnt, hipMemcpyDeviceToHost, st));
+        if (nblk_total > 0)
+            PCHK(hipMemcpyAsync(hblk.data(), pl->d_blk, sizeof(int) * (size_t)nblk_total, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        constexpr double kBlockShare = 32.0;   // per-block cost in incidences
+        std::vector<double> pre;
+        for (int g = 0; g < ngroups; ++g) {
+            const long long b0 = pl->blk_off[g], n = pl->blk_off[g + 1] - b0;
+            pre.assign((size_t)n + 1, 0.0);
+            for (long long i = 0; i < n; ++i)
+                pre[i + 1] = pre[i] + kBlockShare + (double)hcnt[(size_t)(pl->cnt_base[g] + hblk[(size_t)(b0 + i)])];
+            long long i = 0;
+            pl->xsplit[g][0] = 0;
+            for (int x = 1; x < 8; ++x) {
+                const double target = pre[(size_t)n] * x / 8.0;
+                while (i < n && pre[(size_t)i] < target) ++i;
+                pl->xsplit[g][x] = (int)i;
+            }
+            pl->xsplit[g][8] = (int)n;
+        }
+    }
     if (errf & 2) {
         err = "a truncation sphere reaches beyond 127 cells (fold shift out of range)";
         unsupported = true;
