@@ -268,18 +268,21 @@ static hipError_t batch_t(const TaskRef *tasks, int n, hipStream_t st, unsigned 
                     q.row_cap = row_capacity(emax);
                     q.vz = block_column(pl, l);
                     q.G = pl->geom[l];
+                    int chunk = 0;   // the longest XCD range sets the segment's workgroups
+                    for (int x = 0; x < 9; ++x) q.xs[x] = pl->xsplit_pair[g][x];
+                    for (int x = 0; x < 8; ++x) chunk = std::max(chunk, q.xs[x + 1] - q.xs[x]);
                     if (pl->tri)
                         (t.op == GPW_OP_MAT       ? cl.mats_t
                          : t.op == GPW_OP_GRAD    ? cl.grads_t
                          : t.op == GPW_OP_MAT_TAU ? cl.mtaus_t
                                                   : cl.gtaus_t)
-                            .add(q, np);
+                            .add(q, 8LL * chunk);
                     else
                         (t.op == GPW_OP_MAT       ? cl.mats
                          : t.op == GPW_OP_GRAD    ? cl.grads
                          : t.op == GPW_OP_MAT_TAU ? cl.mtaus
                                                   : cl.gtaus)
-                            .add(q, np);
+                            .add(q, 8LL * chunk);
                 }
             }
         }

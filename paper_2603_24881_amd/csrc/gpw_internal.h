@@ -251,31 +251,18 @@ __device__ inline int axis_block_count(int lo, int hi, int N, int nb)
     return hi < lo ? 0 : axis_block_id(hi, N, nb) - axis_block_id(lo, N, nb) + 1;
 }
 
-// Work item of this workgroup such that each of the 8 XCDs (workgroups are
-// dealt to them round robin) walks one contiguous eighth of a list of n items;
-// the grid holds 8 * ceil(n / 8) workgroups and items >= n do nothing.
-__device__ inline long long xcd_item(long long n)
-{
-    const long long per = (n + 7) / 8;
-    const long long b = blockIdx.x;
-    return (b % 8) * per + b / 8;
-}
+// Workgroups are dealt to the eight XCDs round robin (workgroup b runs on XCD
+// b % 8); a segment's workgroup range is padded to a multiple of 8.
 inline unsigned xcd_grid(long long n) { return (unsigned)(8 * ((n + 7) / 8)); }
 // Workgroup b of a segment whose items are dealt to the eight XCDs in
-// contiguous ranges [xs[x], xs[x + 1]) (workgroup b runs on XCD b % 8): its
-// item, or -1 past its XCD's range.  The segment has 8 max_x (xs[x + 1] - xs[x])
-// workgroups.
+// contiguous ranges [xs[x], xs[x + 1]) of about equal work (each XCD, with its
+// own L2, walks one spatially compact part of the group): its item, or -1 past
+// its XCD's range.  The segment has 8 max_x (xs[x + 1] - xs[x]) workgroups.
 __device__ inline long long xcd_ranged(long long b, const int *xs)
 {
     const int x = (int)(b & 7);
     const long long it = xs[x] + (b >> 3);
     return it < xs[x + 1] ? it : -1;
-}
-// xcd_item for workgroup b of a range of xcd_grid(n) workgroups
-__device__ inline long long xcd_local(long long b, long long n)
-{
-    const long long per = (n + 7) / 8;
-    return (b % 8) * per + b / 8;
 }
 
 struct PsTable {
@@ -341,9 +328,11 @@ struct gpw_plan_s {
     // compacted nonempty blocks per group
     int *d_blk = nullptr;
     long long blk_off[gpw::kMaxGroups + 1] = {};
-    // per group, the nonempty blocks dealt to the eight XCDs: contiguous item
-    // ranges [xsplit[g][x], xsplit[g][x + 1]) of about equal work
+    // per group, the nonempty blocks (collocation) and the pair images
+    // (pair-major kernels) dealt to the eight XCDs: contiguous item ranges
+    // [xsplit[g][x], xsplit[g][x + 1]) of about equal work
     int xsplit[gpw::kMaxGroups][9] = {};
+    int xsplit_pair[gpw::kMaxGroups][9] = {};
 
     gpw_plan_info info{};
     int max_axis_blocks = 0;   // longest per-axis block list of a pair image

@@ -80,10 +80,9 @@ struct PackSeg {
 // src) rewritten on the monomials of the index offset into dst (stride cs)
 struct IdxSeg { long long item0; const double *src; void *dst; long long count; int L, K, cs; const TriGeom *tri; };
 // one wave per grid block (rho) or per pair image (mat, grad)
-// Their workgroup ranges are padded to multiples of 8 and mapped to items
-// with xcd_item inside the segment, so that every segment (a level of a
-// task) is spread over all eight XCDs in contiguous chunks, as a launch of
-// its own would be.
+// Their items are mapped with xcd_ranged inside the segment, so that every
+// segment (a level of a task) is spread over all eight XCDs in contiguous
+// ranges of about equal work, as a launch of its own would be.
 struct RhoSeg {
     long long item0;
     long long count;             // nonempty blocks
@@ -109,6 +108,7 @@ struct PairSeg {
     double *out;                 // mat: M; grad: natm x 3
     int n_ao, emax, vz;
     int row_cap;                 // block rows the LDS holds (row_capacity(emax))
+    int xs[9];                   // items of the eight XCDs (xcd_ranged), balanced by work
     LevelGeom G;
 };
 
@@ -1904,8 +1904,8 @@ k_mat(SegTable<PairSeg> tab)
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
-    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
-    if (item >= sg.count) return;
+    const long long item = xcd_ranged(blockIdx.x - sg.item0, sg.xs);
+    if (item < 0) return;
     const LevelGeom &G = sg.G;
     const int n_ao = sg.n_ao;
     const PairRec &r = sg.pairs[item];
@@ -2053,8 +2053,8 @@ k_grad(SegTable<PairSeg> tab)
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
-    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
-    if (item >= sg.count) return;
+    const long long item = xcd_ranged(blockIdx.x - sg.item0, sg.xs);
+    if (item < 0) return;
     const LevelGeom &G = sg.G;
     const int n_ao = sg.n_ao;
     const PairRec &r = sg.pairs[item];
@@ -2169,8 +2169,8 @@ k_mat_tau(SegTable<PairSeg> tab)
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
-    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
-    if (item >= sg.count) return;
+    const long long item = xcd_ranged(blockIdx.x - sg.item0, sg.xs);
+    if (item < 0) return;
     const PairRec &r = sg.pairs[item];
     const double *mom = pair_moments<LA + LB + 2, T, TRI>(sg, r, smem_raw);
     double AB[3];
@@ -2201,8 +2201,8 @@ k_grad_tau(SegTable<PairSeg> tab)
     constexpr int NA = ncart_c(LA), NB = ncart_c(LB);
     extern __shared__ unsigned char smem_raw[];
     const PairSeg &sg = tab.s[seg_of(tab, blockIdx.x)];
-    const long long item = xcd_local(blockIdx.x - sg.item0, sg.count);
-    if (item >= sg.count) return;
+    const long long item = xcd_ranged(blockIdx.x - sg.item0, sg.xs);
+    if (item < 0) return;
     const PairRec &r = sg.pairs[item];
     const double *mom = pair_moments<LA + LB + 3, T, TRI>(sg, r, smem_raw);
     double AB[3];

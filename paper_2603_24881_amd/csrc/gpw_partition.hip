@@ -187,7 +187,7 @@ template <bool FILL>
 __global__ void __launch_bounds__(256)
 k_incidences(const PairRec *pairs, long long npairs, PlanConst pc, const long long *cnt_base_g,
              unsigned *counters, const long long *offsets, unsigned *cursors, int2 *entries,
-             double *stats, int *maxw, int *err_flag)
+             double *stats, int *maxw, int *err_flag, int *work = nullptr)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
@@ -270,6 +270,7 @@ k_incidences(const PairRec *pairs, long long npairs, PlanConst pc, const long lo
         atomicMax(&maxw[1], nbl);
         atomicAdd(&stats[2 * g + 0], (double)npts);
         atomicAdd(&stats[2 * g + 1], (double)ninc);
+        if (work) work[p] = (int)ninc;
     }
 }
 
@@ -589,6 +590,8 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     PCHK(tmp.alloc(&d_cnt_base, sizeof(long long) * (kMaxGroups + 1)));
     PCHK(hipMemcpyAsync(d_cnt_base, pl->cnt_base, sizeof(long long) * (kMaxGroups + 1), hipMemcpyHostToDevice, st));
     PCHK(tmp.alloc(&d_cnt, sizeof(unsigned) * (size_t)(ncnt + 1)));
+    int *d_work = nullptr;   // incidences per pair image
+    PCHK(tmp.alloc(&d_work, sizeof(int) * (size_t)(pl->n_pairs > 0 ? pl->n_pairs : 1)));
     PCHK(tmp.alloc(&d_cur, sizeof(unsigned) * (size_t)(ncnt + 1)));
     PCHK(tmp.alloc(&d_flags, sizeof(unsigned) * (size_t)(ncnt + 1)));
     PCHK(tmp.alloc(&d_flag_off, sizeof(long long) * (size_t)(ncnt + 2)));
@@ -600,7 +603,8 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
     if (pl->n_pairs > 0) {
         hipLaunchKernelGGL(k_incidences<false>, dim3(nblk(pl->n_pairs, 256)), dim3(256), 0, st,
                            (const PairRec *)pl->d_pairs, pl->n_pairs, in.pc, (const long long *)d_cnt_base,
-                           d_cnt, (const long long *)nullptr, (unsigned *)nullptr, (int2 *)nullptr, d_stats, d_maxw, d_err);
+                           d_cnt, (const long long *)nullptr, (unsigned *)nullptr, (int2 *)nullptr, d_stats, d_maxw, d_err,
+                           d_work);
         PCHK(hipGetLastError());
     }
     PCHK(exclusive_scan<unsigned>(d_cnt, ncnt, pl->d_inc_off, st));
@@ -671,6 +675,26 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
                 pl->xsplit[g][x] = (int)i;
             }
             pl->xsplit[g][8] = (int)n;
+        }
+        // the pair images of each group likewise, by their block count (the
+        // traversal) plus a fixed per-image share (set-up and reduction)
+        constexpr double kPairShare = 4.0;
+        std::vector<int> hwork((size_t)pl->n_pairs);
+        if (pl->n_pairs > 0)
+            PCHK(hipMemcpyAsync(hwork.data(), d_work, sizeof(int) * (size_t)pl->n_pairs, hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        for (int g = 0; g < ngroups; ++g) {
+            const long long p0 = pl->group_off[g], n = pl->group_off[g + 1] - p0;
+            pre.assign((size_t)n + 1, 0.0);
+            for (long long i = 0; i < n; ++i) pre[i + 1] = pre[i] + kPairShare + (double)hwork[(size_t)(p0 + i)];
+            long long i = 0;
+            pl->xsplit_pair[g][0] = 0;
+            for (int x = 1; x < 8; ++x) {
+                const double target = pre[(size_t)n] * x / 8.0;
+                while (i < n && pre[(size_t)i] < target) ++i;
+                pl->xsplit_pair[g][x] = (int)i;
+            }
+            pl->xsplit_pair[g][8] = (int)n;
         }
     }
     if (errf & 2) {
