@@ -17,6 +17,8 @@
 //    offsets and compact the nonempty blocks of every group.
 #include "gpw_internal.h"
 
+#include <algorithm>
+
 namespace gpw {
 
 __device__ inline int level_for(const PlanConst &pc, double alpha_p)
@@ -675,7 +677,16 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
                 pl->xsplit[g][x] = (int)i;
             }
             pl->xsplit[g][8] = (int)n;
+            // inside each XCD's range the longest lists first, so that the
+            // range does not end on a long block (about 1 % of eval_rho)
+            for (int x = 0; x < 8; ++x) {
+                int *beg = hblk.data() + b0 + pl->xsplit[g][x], *end = hblk.data() + b0 + pl->xsplit[g][x + 1];
+                const long long cb = pl->cnt_base[g];
+                std::stable_sort(beg, end, [&](int u, int v) { return hcnt[(size_t)(cb + u)] > hcnt[(size_t)(cb + v)]; });
+            }
         }
+        if (nblk_total > 0)
+            PCHK(hipMemcpyAsync(pl->d_blk, hblk.data(), sizeof(int) * (size_t)nblk_total, hipMemcpyHostToDevice, st));
         // the pair images of each group likewise, by their block count (the
         // traversal) plus a fixed per-image share (set-up and reduction)
         constexpr double kPairShare = 4.0;
