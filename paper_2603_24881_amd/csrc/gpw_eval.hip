@@ -48,8 +48,9 @@ __global__ void __launch_bounds__(256) k_fill(SegTable<FillSeg> tab)
 }
 
 // Copy of a level grid in 4x4x4-block order (block b = (kx nb1 + ky) vz + kz,
-// then the 64 points with the z index fastest), zero at the padding points
-// of partial blocks, so that one wave reads a block with one coalesced load.
+// then the 64 points as four z planes of 16 points, y fastest), zero at the
+// padding points of partial blocks, so that one plane of a block is one
+// 128-byte line and the planes of a run of blocks along z are consecutive.
 // Each (x, y) column holds vz >= nb2 blocks: past its nb2 blocks it repeats
 // the column periodically, so that a run of up to vz - nb2 + 1 blocks along z
 // that starts in the cell is contiguous in memory.
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__(256) k_block_grid(SegTable<GridSeg> tab)
     const int kz = (int)(b % sg.vz) % G.nb[2];
     const int ky = (int)((b / sg.vz) % G.nb[1]);
     const int kx = (int)(b / ((long long)sg.vz * G.nb[1]));
-    const int wx = 4 * kx + (t >> 4), wy = 4 * ky + ((t >> 2) & 3), wz = 4 * kz + (t & 3);
+    const int wx = 4 * kx + ((t >> 2) & 3), wy = 4 * ky + (t & 3), wz = 4 * kz + (t >> 4);
     vb[i] = (wx < G.N[0] && wy < G.N[1] && wz < G.N[2]) ? v[((long long)wx * G.N[1] + wy) * G.N[2] + wz] : 0.0;
 }
 

@@ -1164,6 +1164,10 @@ template <typename T> struct alignas(4 * sizeof(T)) PtZ { T e, a, b, c; };
 // shifts) its bounding box meets, one entry per lane, and the point tables of
 // the entries, so that the points of a run of consecutive entries sit at
 // consecutive table positions.  emax bounds every list (the plan's longest).
+// The z table has 8 emax entries: past the box's 4 nz points it holds points
+// that no sphere contains (envelope factor 0; TRI: an offset of 1e18, whose
+// squared metric length exceeds any R^2 and stays finite in FP32), so that a
+// traversal may step past the end of a run without a bounds test.
 // TRI (a general cell, index units): the tables hold the offset from P in
 // place of the envelope factor (the envelope does not separate; the visitor
 // forms it per point), and the gaps are scaled by the metric's smallest
@@ -1216,6 +1220,7 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             }
         }
     }
+    for (int i = 4 * r.bn[2] + threadIdx.x; i < 8 * emax; i += 64) tz[i] = PtZ<T>{TRI ? T(1e18) : T(0), T(0), T(0), T(0)};
     if (threadIdx.x == 0) {
         cnt[0] = r.bn[0];
         cnt[1] = r.bn[1];
@@ -1235,11 +1240,14 @@ struct BlockRow {
     int zn;    // zlo | n << 16
 };
 
-// Rows of the pair image's blocks with x entries in [ex0, ex1), in (x block,
-// y block) order: built by the wave with one candidate row per lane and a
-// ballot compaction.
+// Rows of the pair image's blocks with x entries in [ex0, ex1), longest run
+// first: built by the wave with one candidate row per lane and a ballot
+// compaction into tmp, then placed by a counting sort on the run length
+// (hist: emax + 1 counters), so that the rows a traversal takes four at a
+// time have runs of about the same length.
 __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, int vz, const AxisBlock *bl,
-                                          int emax, const int *cnt, BlockRow *rows, int ex0, int ex1)
+                                          int emax, const int *cnt, BlockRow *rows, BlockRow *tmp, int *hist,
+                                          int ex0, int ex1)
 {
     const int lane = threadIdx.x;
     const int ny = uni(cnt[1]), nz = uni(cnt[2]), em = uni(cnt[3]);
@@ -1287,75 +1295,109 @@ __device__ __forceinline__ int build_rows(const double R2c, const LevelGeom &G, 
             }
         }
         const unsigned long long m = __ballot(ok);
-        if (ok) rows[nrows + __popcll(m & ((1ull << lane) - 1))] = row;
+        if (ok) tmp[nrows + __popcll(m & ((1ull << lane) - 1))] = row;
         nrows += __popcll(m);
+    }
+    for (int k = lane; k <= emax; k += 64) hist[k] = 0;
+    __syncthreads();
+    for (int i = lane; i < nrows; i += 64) atomicAdd(&hist[tmp[i].zn >> 16], 1);
+    __syncthreads();
+    // first position of each length: the rows of greater length before it
+    // (a wave scan over the lengths from emax down, 64 at a time)
+    int carry = 0;
+    for (int top = emax; top >= 1; top -= 64) {
+        const int n = top - lane;
+        const int h = n >= 1 ? hist[n] : 0;
+        int sc = h;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(sc, d, 64);
+            if (lane >= d) sc += t;
+        }
+        if (n >= 1) hist[n] = carry + sc - h;
+        carry += __shfl(sc, 63, 64);
+    }
+    __syncthreads();
+    for (int i = lane; i < nrows; i += 64) {
+        const BlockRow w = tmp[i];
+        rows[atomicAdd(&hist[w.zn >> 16], 1)] = w;
     }
     return nrows;
 }
 
 // Visit every (block, shift) incidence of the pair image whose block meets
-// the truncation sphere (the incidences the partitioner lists), lane = point
-// of the block, row by row in (x, y, z) block order.  Blocks are taken four
-// at a time along a row's z run, which is contiguous both in the block copy
-// and in the z table.  The potential of the next four blocks is loaded
-// before the current four are used, so that the load latency overlaps the
-// arithmetic; the loads always cover four whole blocks (the block copy has
-// kBlockCopyTail blocks of slack at its end), which keeps their number fixed.
-// The visitor sees vis.row(ex, X, Y) at the start of every row (X, Y: the
-// lane's x and y table entries) and vis.point(v, Z) for every point (v the
-// potential, Z the lane's z table entry), then vis.done().
+// the truncation sphere (the incidences the partitioner lists), four block
+// rows at a time: lane = (row slot g of the group, point (tx, ty) of the
+// 4x4 cross-section of the row's blocks).  The wave steps along z one point
+// plane at a time, through the runs of all four rows together; a row shorter
+// than the group's longest (the first, rows being sorted longest first) and
+// an empty slot of the last group step on past their end over points that no
+// sphere contains (the z table's padding, or points of blocks beyond the run,
+// which the sphere cut removes), and an empty slot's lanes are cut by the
+// visitor.  The block copy holds each block's points as four z planes of
+// 16 (x, y) points, so that a plane of a run is one 128-byte line per row and
+// the run is contiguous; reads past a run's end stay inside its column
+// (at most emax blocks from a start inside the cell).  The potential of the
+// next block's four planes is loaded before the current one is used.
+// The visitor sees vis.row(X, Y, ok) at the start of every group (X, Y: the
+// lane's x and y table entries; ok: the lane's slot holds a row) and
+// vis.point(v, Z) for every point (v the potential, Z the z table entry),
+// then vis.done().
 template <typename T, typename Vis>
 __device__ __forceinline__ void for_each_point(const PtXY<T> *txy, const PtZ<T> *tzt, int emax, const BlockRow *rows,
                                                int nrows, const double *__restrict__ Vb, Vis &vis)
 {
     const int lane = threadIdx.x;
-    const int E4 = 4 * emax;
-    const PtXY<T> *px = txy + (lane >> 4), *py = txy + E4 + ((lane >> 2) & 3);
-    const PtZ<T> *pz = tzt + (lane & 3);
+    const int g = lane >> 4, col = lane & 15;
+    const PtXY<T> *px = txy + (col >> 2), *py = txy + 4 * emax + (col & 3);
     if (nrows <= 0) return;
-    // batch cursor: row rr, its fields, offset i0 of the batch in the run
+    // cursor: group (first row q), block b of the runs, the group's longest
+    // run; per lane: its row's potential column, z table position and x, y
+    // entries
     struct Cur {
-        int rr, i0, vb, ex, ey, zn;
+        int q, b, nmax;
+        const double *vp;
+        int zi, ex, ey;
+        bool ok;
     };
-    auto fetch_row = [&](Cur &c) {
-        const BlockRow w = rows[c.rr];
-        c.vb = uni(w.vb);
-        c.ex = uni(w.ex);
-        c.ey = uni(w.ey);
-        c.zn = uni(w.zn);
+    auto fetch_group = [&](Cur &c, int q) {
+        const int slot = q + g;
+        c.q = q;
+        c.b = 0;
+        c.ok = slot < nrows;
+        const BlockRow w = rows[c.ok ? slot : q];
+        c.nmax = uni(w.zn >> 16);   // lane 0 holds row q, the group's longest
+        c.vp = Vb + (long long)w.vb * 64 + col;
+        c.zi = 4 * (w.zn & 0xffff);
+        c.ex = w.ex;
+        c.ey = w.ey;
     };
     auto load4 = [&](const Cur &c, double *v) {
-        const double *p = Vb + (long long)(c.vb + c.i0) * 64 + lane;
+        const double *p = c.vp + (long long)c.b * 64;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = p[u * 64];
+        for (int u = 0; u < 4; ++u) v[u] = p[u * 16];
     };
-    // advance c to the next batch; false at the end (c then stays put)
+    // advance c to the next block; false at the end (c then stays put)
     auto advance = [&](Cur &c) {
-        if (c.i0 + 4 < (c.zn >> 16)) {
-            c.i0 += 4;
+        if (c.b + 1 < c.nmax) {
+            c.b += 1;
             return true;
         }
-        if (c.rr + 1 >= nrows) return false;
-        c.rr += 1;
-        c.i0 = 0;
-        fetch_row(c);
+        if (c.q + 4 >= nrows) return false;
+        fetch_group(c, c.q + 4);
         return true;
     };
     auto run = [&](const Cur &c, const double *v) {
-        if (c.i0 == 0) vis.row(c.ex, px[4 * c.ex], py[4 * c.ey]);
-        const PtZ<T> *z = pz + 4 * ((c.zn & 0xffff) + c.i0);
-        const int m = (c.zn >> 16) - c.i0;
+        if (c.b == 0) vis.row(px[4 * c.ex], py[4 * c.ey], c.ok);
+        const PtZ<T> *z = tzt + c.zi + 4 * c.b;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (u < m) vis.point((T)v[u], z[4 * u]);
+        for (int u = 0; u < 4; ++u) vis.point((T)v[u], z[u]);
     };
     Cur a;
-    a.rr = 0;
-    a.i0 = 0;
-    fetch_row(a);
+    fetch_group(a, 0);
     double va[4], vb4[4];
     load4(a, va);
-    // two batches per trip, alternating the two potential buffers
+    // two blocks per trip, alternating the two potential buffers
     for (;;) {
         Cur b = a;
         const bool mb = advance(b);
@@ -1378,20 +1420,22 @@ template <typename T, typename Body>
 struct DirectVisit {
     Body &body;
     T ER, abx, aby;
-    T xa = 0, ya = 0, xb = 0, yb = 0, exy = 0;
+    T xa = 0, ya = 0, xb = 0, yb = 0, exy = 0, er = 0;
     __device__ DirectVisit(Body &b, const PairRec &r) : body(b), ER((T)r.ER), abx((T)r.AB[0]), aby((T)r.AB[1]) {}
-    __device__ __forceinline__ void row(int, const PtXY<T> &X, const PtXY<T> &Y)
+    // ok = false: a lane without a row, every point cut
+    __device__ __forceinline__ void row(const PtXY<T> &X, const PtXY<T> &Y, bool ok)
     {
         xa = X.a;
         ya = Y.a;
         xb = xa + abx;
         yb = ya + aby;
         exy = X.e * Y.e;
+        er = ok ? ER : T(__builtin_huge_val());
     }
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T E = exy * Z.e;
-        body((E >= ER) ? v * E : T(0), xa, ya, Z.a, xb, yb, Z.b);
+        body((E >= er) ? v * E : T(0), xa, ya, Z.a, xb, yb, Z.b);
     }
     __device__ __forceinline__ void done() {}
 };
@@ -1399,71 +1443,54 @@ struct DirectVisit {
 // Visitor of the separable form (the potential analogue of Eq. (rho1)): the
 // moments sum_r v(r) E(r) (x-A_x)^lx (y-A_y)^ly (z-A_z)^lz of total degree
 // <= L, accumulated one axis at a time: per point the z moments of the
-// lane's current (x, y) column (W), at the end of a row the (y, z) moments
-// of the lane's x slice (U), when the row's x block changes the full
-// moments (Vm).  E(r) = ex ey ez is split the same way; the sphere cut uses
-// the full product.
+// lane's current (x, y) column (W), at the end of a group of rows the full
+// moments (Vm += W_lz ex ey (x-A_x)^lx (y-A_y)^ly).  E(r) = ex ey ez is
+// split the same way; the sphere cut uses the full product.
 template <int L, typename T>
 struct TensorVisit {
-    static constexpr int K = ntab(L), K2 = ntab2(L);
-    T Vm[K], U[K2], W[L + 1];
+    static constexpr int K = ntab(L);
+    T Vm[K], W[L + 1];
     T ER;
-    T xa = 0, ex = 0, ya = 0, ey = 0, exy = 0;
-    int xcur = -1;
+    T xa = 0, ya = 0, exy = 0, er = 0;
     __device__ TensorVisit(const PairRec &r, const LevelGeom &) : TensorVisit(r) {}
     __device__ explicit TensorVisit(const PairRec &r) : ER((T)r.ER)
     {
 #pragma unroll
         for (int k = 0; k < K; ++k) Vm[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < K2; ++k) U[k] = T(0);
-#pragma unroll
         for (int k = 0; k <= L; ++k) W[k] = T(0);
     }
-    __device__ __forceinline__ void flush_row()
+    __device__ __forceinline__ void flush()
     {
-        T g = ey;
-#pragma unroll
-        for (int ly = 0; ly <= L; ++ly) {
-#pragma unroll
-            for (int lz = 0; ly + lz <= L; ++lz) U[t2idx(L, ly, lz)] += W[lz] * g;
-            g *= ya;
-        }
-#pragma unroll
-        for (int k = 0; k <= L; ++k) W[k] = T(0);
-    }
-    __device__ __forceinline__ void flush_x()
-    {
-        T g = ex;
+        T gx = exy;   // ex ey (x-A_x)^lx
 #pragma unroll
         for (int lx = 0; lx <= L; ++lx) {
+            T g = gx;
 #pragma unroll
-            for (int ly = 0; lx + ly <= L; ++ly)
+            for (int ly = 0; lx + ly <= L; ++ly) {
 #pragma unroll
-                for (int lz = 0; lx + ly + lz <= L; ++lz) Vm[tidx(L, lx, ly, lz)] += U[t2idx(L, ly, lz)] * g;
-            g *= xa;
+                for (int lz = 0; lx + ly + lz <= L; ++lz) Vm[tidx(L, lx, ly, lz)] += W[lz] * g;
+                g *= ya;
+            }
+            gx *= xa;
         }
 #pragma unroll
-        for (int k = 0; k < K2; ++k) U[k] = T(0);
+        for (int k = 0; k <= L; ++k) W[k] = T(0);
     }
-    __device__ __forceinline__ void row(int exn, const PtXY<T> &X, const PtXY<T> &Y)
+    // ok = false: a lane without a row, every point cut
+    __device__ __forceinline__ void row(const PtXY<T> &X, const PtXY<T> &Y, bool ok)
     {
-        if (xcur >= 0) {
-            flush_row();
-            if (exn != xcur) flush_x();
-        }
-        xcur = exn;
+        flush();
         xa = X.a;
-        ex = X.e;
         ya = Y.a;
-        ey = Y.e;
-        exy = ex * ey;
+        exy = X.e * Y.e;
+        er = ok ? ER : T(__builtin_huge_val());
     }
     // Z.b, Z.c hold (z - A_z)^2 and (z - A_z)^3
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T E = exy * Z.e;
-        const T f = (E >= ER) ? v * Z.e : T(0);
+        const T f = (E >= er) ? v * Z.e : T(0);
         W[0] += f;
         if constexpr (L >= 1) W[1] += f * Z.a;
         if constexpr (L >= 2) W[2] += f * Z.b;
@@ -1477,13 +1504,7 @@ struct TensorVisit {
             }
         }
     }
-    __device__ __forceinline__ void done()
-    {
-        if (xcur >= 0) {
-            flush_row();
-            flush_x();
-        }
-    }
+    __device__ __forceinline__ void done() { flush(); }
 };
 
 template <typename T> __device__ __forceinline__ T texp(T x);
@@ -1498,12 +1519,11 @@ template <> __device__ __forceinline__ float texp<float>(float x) { return expf(
 // TensorVisit, with the envelope applied per point.
 template <int L, typename T>
 struct TensorVisitTri {
-    static constexpr int K = ntab(L), K2 = ntab2(L);
-    T Vm[K], U[K2], W[L + 1];
+    static constexpr int K = ntab(L);
+    T Vm[K], W[L + 1];
     T R2, nap;
     T gxx, gyy, gzz, gxy2, gxz2, gyz2;   // metric, off-diagonal terms doubled
-    T xa = 0, ya = 0, qrow = 0, crow = 0;
-    int xcur = -1;
+    T xa = 0, ya = 0, qrow = 0, crow = 0, r2 = 0;
     __device__ TensorVisitTri(const PairRec &r, const LevelGeom &G) : R2((T)r.R2), nap((T)(-(r.aa + r.ab)))
     {
         const double(*g)[3] = G.tri->g;
@@ -1516,55 +1536,42 @@ struct TensorVisitTri {
 #pragma unroll
         for (int k = 0; k < K; ++k) Vm[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < K2; ++k) U[k] = T(0);
-#pragma unroll
         for (int k = 0; k <= L; ++k) W[k] = T(0);
     }
-    __device__ __forceinline__ void flush_row()
+    __device__ __forceinline__ void flush()
     {
-        T g = T(1);
-#pragma unroll
-        for (int ly = 0; ly <= L; ++ly) {
-#pragma unroll
-            for (int lz = 0; ly + lz <= L; ++lz) U[t2idx(L, ly, lz)] += W[lz] * g;
-            g *= ya;
-        }
-#pragma unroll
-        for (int k = 0; k <= L; ++k) W[k] = T(0);
-    }
-    __device__ __forceinline__ void flush_x()
-    {
-        T g = T(1);
+        T gx = T(1);   // (x-A_x)^lx
 #pragma unroll
         for (int lx = 0; lx <= L; ++lx) {
+            T g = gx;
 #pragma unroll
-            for (int ly = 0; lx + ly <= L; ++ly)
+            for (int ly = 0; lx + ly <= L; ++ly) {
 #pragma unroll
-                for (int lz = 0; lx + ly + lz <= L; ++lz) Vm[tidx(L, lx, ly, lz)] += U[t2idx(L, ly, lz)] * g;
-            g *= xa;
+                for (int lz = 0; lx + ly + lz <= L; ++lz) Vm[tidx(L, lx, ly, lz)] += W[lz] * g;
+                g *= ya;
+            }
+            gx *= xa;
         }
 #pragma unroll
-        for (int k = 0; k < K2; ++k) U[k] = T(0);
+        for (int k = 0; k <= L; ++k) W[k] = T(0);
     }
-    // X.e, Y.e: offsets from P; X.a, Y.a: offsets from A
-    __device__ __forceinline__ void row(int exn, const PtXY<T> &X, const PtXY<T> &Y)
+    // X.e, Y.e: offsets from P; X.a, Y.a: offsets from A; ok = false: a lane
+    // without a row, every point cut (q >= 0 > -1)
+    __device__ __forceinline__ void row(const PtXY<T> &X, const PtXY<T> &Y, bool ok)
     {
-        if (xcur >= 0) {
-            flush_row();
-            if (exn != xcur) flush_x();
-        }
-        xcur = exn;
+        flush();
         xa = X.a;
         ya = Y.a;
         const T dx = X.e, dy = Y.e;
         qrow = gxx * dx * dx + gxy2 * dx * dy + gyy * dy * dy;
         crow = gxz2 * dx + gyz2 * dy;
+        r2 = ok ? R2 : T(-1);
     }
     // Z.e: z offset from P; Z.a, Z.b, Z.c: (z - A_z), its square and cube
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T q = qrow + Z.e * (gzz * Z.e + crow);
-        const T f = (q <= R2) ? v * texp<T>(nap * q) : T(0);
+        const T f = (q <= r2) ? v * texp<T>(nap * q) : T(0);
         W[0] += f;
         if constexpr (L >= 1) W[1] += f * Z.a;
         if constexpr (L >= 2) W[2] += f * Z.b;
@@ -1578,13 +1585,7 @@ struct TensorVisitTri {
             }
         }
     }
-    __device__ __forceinline__ void done()
-    {
-        if (xcur >= 0) {
-            flush_row();
-            flush_x();
-        }
-    }
+    __device__ __forceinline__ void done() { flush(); }
 };
 
 // Cartesian moments of a general cell's pair image from those of the index
@@ -1646,30 +1647,43 @@ __host__ __device__ constexpr int row_capacity(int emax)
     return emax * emax <= kRowCap ? emax * emax : (kRowCap > emax ? kRowCap : emax);
 }
 
-// LDS layout of the pair-major kernels: the x and y point tables
-// txy[2][4 emax], the z point table tz[4 emax], then the block lists
-// bl[3][emax], their counts and the block rows (row_capacity(emax)).
+// LDS layout of the pair-major kernels: the z point table tz[8 emax] (its
+// second half padding), the x and y point tables txy[2][4 emax], the block
+// lists bl[3][emax], their counts, the run-length counters hist[emax + 1],
+// and the block rows and their unsorted copy (row_capacity(emax) each).
+template <typename T>
+struct PairLds {
+    PtXY<T> *txy;
+    PtZ<T> *tz;
+    AxisBlock *bl;
+    int *cnt, *hist;
+    BlockRow *rows, *tmp;
+};
 template <typename T>
 struct PairSmem {
     static __host__ __device__ size_t table_bytes(int emax)
     {
-        const size_t b = (2 * sizeof(PtXY<T>) + sizeof(PtZ<T>)) * 4 * (size_t)emax;
+        const size_t b = (8 * sizeof(PtXY<T>) + 8 * sizeof(PtZ<T>)) * (size_t)emax;
         return (b + 15) & ~size_t(15);
     }
-    static __device__ __forceinline__ void carve(unsigned char *raw, int emax, PtXY<T> *&txy, PtZ<T> *&tz,
-                                                 AxisBlock *&bl, int *&cnt, BlockRow *&rows)
+    static __host__ __device__ size_t hist_ints(int emax) { return ((size_t)emax + 1 + 3) & ~size_t(3); }
+    static __device__ __forceinline__ PairLds<T> carve(unsigned char *raw, int emax)
     {
-        tz = reinterpret_cast<PtZ<T> *>(raw);
-        txy = reinterpret_cast<PtXY<T> *>(tz + 4 * emax);
-        bl = reinterpret_cast<AxisBlock *>(raw + table_bytes(emax));
-        cnt = reinterpret_cast<int *>(bl + 3 * emax);
-        rows = reinterpret_cast<BlockRow *>(cnt + 4);
+        PairLds<T> l;
+        l.tz = reinterpret_cast<PtZ<T> *>(raw);
+        l.txy = reinterpret_cast<PtXY<T> *>(l.tz + 8 * emax);
+        l.bl = reinterpret_cast<AxisBlock *>(raw + table_bytes(emax));
+        l.cnt = reinterpret_cast<int *>(l.bl + 3 * emax);
+        l.hist = l.cnt + 4;
+        l.rows = reinterpret_cast<BlockRow *>(l.hist + hist_ints(emax));
+        l.tmp = l.rows + row_capacity(emax);
+        return l;
     }
     static size_t bytes(int emax, bool tri = false)
     {
         const size_t off = table_bytes(emax);
-        const size_t b =
-            off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(BlockRow) * (size_t)row_capacity(emax);
+        const size_t b = off + sizeof(AxisBlock) * 3 * (size_t)emax + 16 + sizeof(int) * hist_ints(emax) +
+                         2 * sizeof(BlockRow) * (size_t)row_capacity(emax);
         const size_t red = tri ? kRedBytesTri : kRedBytes;
         return b > red ? b : red;   // the area is reused for the final reduction
     }
@@ -1679,17 +1693,15 @@ struct PairSmem {
 // the LDS rows (one slice unless the box is wider than kRowCap rows); the
 // visitor's state carries over from slice to slice.  Ends with a barrier.
 template <typename T, typename Vis>
-__device__ __forceinline__ void traverse_slices(const PairRec &r, const PairSeg &sg, const PtXY<T> *txy,
-                                                const PtZ<T> *tz, const AxisBlock *bl, const int *cnt,
-                                                BlockRow *rows, Vis &vis)
+__device__ __forceinline__ void traverse_slices(const PairRec &r, const PairSeg &sg, const PairLds<T> &l, Vis &vis)
 {
-    const int nx = uni(cnt[0]), ny = uni(cnt[1]);
+    const int nx = uni(l.cnt[0]), ny = uni(l.cnt[1]);
     const int xs = ny > 0 ? (sg.row_cap / ny > 1 ? sg.row_cap / ny : 1) : nx;
     for (int ex0 = 0; ex0 < nx; ex0 += xs) {
-        const int nrows = build_rows(r.R2 * kCullSlack, sg.G, sg.vz, bl, sg.emax, cnt, rows, ex0,
-                                     ex0 + xs < nx ? ex0 + xs : nx);
+        const int nrows = build_rows(r.R2 * kCullSlack, sg.G, sg.vz, l.bl, sg.emax, l.cnt, l.rows, l.tmp, l.hist,
+                                     ex0, ex0 + xs < nx ? ex0 + xs : nx);
         __syncthreads();
-        for_each_point<T>(txy, tz, sg.emax, rows, nrows, sg.Vb, vis);
+        for_each_point<T>(l.txy, l.tz, sg.emax, l.rows, nrows, sg.Vb, vis);
         __syncthreads();   // the rows are rebuilt for the next slice
     }
 }
@@ -1701,19 +1713,14 @@ __device__ __forceinline__ void traverse_slices(const PairRec &r, const PairSeg 
 template <int LT, typename T, bool TRI = false>
 __device__ __forceinline__ const double *pair_moments(const PairSeg &sg, const PairRec &r, unsigned char *smem_raw)
 {
-    PtXY<T> *txy;
-    PtZ<T> *tz;
-    AxisBlock *bl;
-    int *cnt;
-    BlockRow *rows;
     const LevelGeom &G = sg.G;
     const int emax = sg.emax;
-    PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
-    pair_setup<true, T, TRI>(r, G, txy, tz, bl, emax, cnt);
+    const PairLds<T> l = PairSmem<T>::carve(smem_raw, emax);
+    pair_setup<true, T, TRI>(r, G, l.txy, l.tz, l.bl, emax, l.cnt);
     __syncthreads();
     using Vis = std::conditional_t<TRI, TensorVisitTri<LT, T>, TensorVisit<LT, T>>;
     Vis vis(r, G);
-    traverse_slices<T>(r, sg, txy, tz, bl, cnt, rows, vis);
+    traverse_slices<T>(r, sg, l, vis);
     // the traversal's LDS reads are done; the area becomes red[8][65]
     double *red = reinterpret_cast<double *>(smem_raw);
     double *mom = red + 8 * 65;
@@ -1911,14 +1918,9 @@ k_mat(SegTable<PairSeg> tab)
     const PairRec &r = sg.pairs[item];
     const double scale = 0.5 * G.w * r.Kw;
     if constexpr (!TRI && !mat_tensor(LA, LB)) {
-        PtXY<T> *txy;
-        PtZ<T> *tz;
-        AxisBlock *bl;
-        int *cnt;
-        BlockRow *rows;
         const int emax = sg.emax;
-        PairSmem<T>::carve(smem_raw, emax, txy, tz, bl, cnt, rows);
-        pair_setup<false, T>(r, G, txy, tz, bl, emax, cnt);
+        const PairLds<T> l = PairSmem<T>::carve(smem_raw, emax);
+        pair_setup<false, T>(r, G, l.txy, l.tz, l.bl, emax, l.cnt);
         __syncthreads();
         T acc[NA * NB];
 #pragma unroll
@@ -1935,7 +1937,7 @@ k_mat(SegTable<PairSeg> tab)
             }
         };
         DirectVisit<T, decltype(body)> vis(body, r);
-        traverse_slices<T>(r, sg, txy, tz, bl, cnt, rows, vis);
+        traverse_slices<T>(r, sg, l, vis);
         // the traversal's LDS reads are done; the area becomes red[8][65]
         wave_reduce_emit<NA * NB, T>(acc, reinterpret_cast<double *>(smem_raw), [&](int k, double v) {
             const int i = k / NB, j = k - (k / NB) * NB;
