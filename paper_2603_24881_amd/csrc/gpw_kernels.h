@@ -1413,6 +1413,17 @@ __device__ __forceinline__ void for_each_point(const PtXY<T> *txy, const PtZ<T> 
     vis.done();
 }
 
+// f where keep holds, else a value of magnitude below 2^-1022 (FP64: the
+// high word cleared, one select instead of two; FP32: 0).  Accumulated over
+// at most a pair image's points, such values stay below 1e-300.
+__device__ __forceinline__ double keep_if(double f, bool keep)
+{
+    const long long b = __double_as_longlong(f);
+    const int hi = keep ? (int)(b >> 32) : 0;
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)(b & 0xffffffffLL));
+}
+__device__ __forceinline__ float keep_if(float f, bool keep) { return keep ? f : 0.0f; }
+
 // Visitor of the direct form: body(f, xa, ya, za, xb, yb, zb) per point with
 // f = v(r) exp(-alpha_p |r-P|^2) inside the sphere, else 0, (xa, ya, za) =
 // r - A and (xb, yb, zb) = r - B.
@@ -1435,7 +1446,7 @@ struct DirectVisit {
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T E = exy * Z.e;
-        body((E >= er) ? v * E : T(0), xa, ya, Z.a, xb, yb, Z.b);
+        body(keep_if(v * E, E >= er), xa, ya, Z.a, xb, yb, Z.b);
     }
     __device__ __forceinline__ void done() {}
 };
@@ -1451,7 +1462,7 @@ struct TensorVisit {
     static constexpr int K = ntab(L);
     T Vm[K], W[L + 1];
     T ER;
-    T xa = 0, ya = 0, exy = 0, er = 0;
+    T xa = 0, ya = 0, exy = 0, thr = 0;
     __device__ TensorVisit(const PairRec &r, const LevelGeom &) : TensorVisit(r) {}
     __device__ explicit TensorVisit(const PairRec &r) : ER((T)r.ER)
     {
@@ -1477,20 +1488,20 @@ struct TensorVisit {
 #pragma unroll
         for (int k = 0; k <= L; ++k) W[k] = T(0);
     }
-    // ok = false: a lane without a row, every point cut
+    // ok = false: a lane without a row, every point cut.  The cut
+    // ex ey ez >= E_R is taken as ez >= E_R / (ex ey) (+inf: none kept).
     __device__ __forceinline__ void row(const PtXY<T> &X, const PtXY<T> &Y, bool ok)
     {
         flush();
         xa = X.a;
         ya = Y.a;
         exy = X.e * Y.e;
-        er = ok ? ER : T(__builtin_huge_val());
+        thr = ok ? ER / exy : T(__builtin_huge_val());
     }
     // Z.b, Z.c hold (z - A_z)^2 and (z - A_z)^3
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
-        const T E = exy * Z.e;
-        const T f = (E >= er) ? v * Z.e : T(0);
+        const T f = keep_if(v * Z.e, Z.e >= thr);
         W[0] += f;
         if constexpr (L >= 1) W[1] += f * Z.a;
         if constexpr (L >= 2) W[2] += f * Z.b;
@@ -1571,7 +1582,7 @@ struct TensorVisitTri {
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T q = qrow + Z.e * (gzz * Z.e + crow);
-        const T f = (q <= r2) ? v * texp<T>(nap * q) : T(0);
+        const T f = keep_if(v * texp<T>(nap * q), q <= r2);
         W[0] += f;
         if constexpr (L >= 1) W[1] += f * Z.a;
         if constexpr (L >= 2) W[2] += f * Z.b;
