@@ -1158,16 +1158,20 @@ __device__ __forceinline__ double uni(double v)
 // offset x - A; along z two more values: for the direct form z - B and 0,
 // for the moment form (z - A)^2 and (z - A)^3.
 template <typename T> struct alignas(2 * sizeof(T)) PtXY { T e, a; };
-template <typename T> struct alignas(4 * sizeof(T)) PtZ { T e, a, b, c; };
+template <typename T> struct alignas(2 * sizeof(T)) PtZ { T e, a; };
+constexpr int kZSlots = 5;   // z table slots per block entry (4 points, 1 unused)
 
 // LDS set-up of one pair image: per axis, the list of the blocks (with fold
 // shifts) its bounding box meets, one entry per lane, and the point tables of
 // the entries, so that the points of a run of consecutive entries sit at
 // consecutive table positions.  emax bounds every list (the plan's longest).
-// The z table has 8 emax entries: past the box's 4 nz points it holds points
-// that no sphere contains (envelope factor 0; TRI: an offset of 1e18, whose
-// squared metric length exceeds any R^2 and stays finite in FP32), so that a
-// traversal may step past the end of a run without a bounds test.
+// The z table holds 8 emax points: past the box's 4 nz points, points that no
+// sphere contains (envelope factor 0; TRI: an offset of 1e18, whose squared
+// metric length exceeds any R^2 and stays finite in FP32), so that a
+// traversal may step past the end of a run without a bounds test.  Point i
+// sits in slot i + i / 4 (kZSlots slots per block entry, one unused): the
+// rows that a traversal reads together start at different entries, and the
+// odd stride puts their points in different LDS banks.
 // TRI (a general cell, index units): the tables hold the offset from P in
 // place of the envelope factor (the envelope does not separate; the visitor
 // forms it per point), and the gaps are scaled by the metric's smallest
@@ -1213,14 +1217,12 @@ __device__ __forceinline__ void pair_setup(const PairRec &r, const LevelGeom &G,
             if (d < 2) {
                 txy[d * 4 * emax + i] = PtXY<T>{(T)e, (T)a};
             } else {
-                if (MOM)
-                    tz[i] = PtZ<T>{(T)e, (T)a, (T)(a * a), (T)(a * a * a)};
-                else
-                    tz[i] = PtZ<T>{(T)e, (T)a, (T)(a + r.AB[2]), T(0)};
+                tz[i + (i >> 2)] = PtZ<T>{(T)e, (T)a};
             }
         }
     }
-    for (int i = 4 * r.bn[2] + threadIdx.x; i < 8 * emax; i += 64) tz[i] = PtZ<T>{TRI ? T(1e18) : T(0), T(0), T(0), T(0)};
+    for (int i = 4 * r.bn[2] + threadIdx.x; i < 8 * emax; i += 64)
+        tz[i + (i >> 2)] = PtZ<T>{TRI ? T(1e18) : T(0), T(0)};
     if (threadIdx.x == 0) {
         cnt[0] = r.bn[0];
         cnt[1] = r.bn[1];
@@ -1368,7 +1370,7 @@ __device__ __forceinline__ void for_each_point(const PtXY<T> *txy, const PtZ<T> 
         const BlockRow w = rows[c.ok ? slot : q];
         c.nmax = uni(w.zn >> 16);   // lane 0 holds row q, the group's longest
         c.vp = Vb + (long long)w.vb * 64 + col;
-        c.zi = 4 * (w.zn & 0xffff);
+        c.zi = kZSlots * (w.zn & 0xffff);
         c.ex = w.ex;
         c.ey = w.ey;
     };
@@ -1389,7 +1391,7 @@ __device__ __forceinline__ void for_each_point(const PtXY<T> *txy, const PtZ<T> 
     };
     auto run = [&](const Cur &c, const double *v) {
         if (c.b == 0) vis.row(px[4 * c.ex], py[4 * c.ey], c.ok);
-        const PtZ<T> *z = tzt + c.zi + 4 * c.b;
+        const PtZ<T> *z = tzt + c.zi + kZSlots * c.b;
 #pragma unroll
         for (int u = 0; u < 4; ++u) vis.point((T)v[u], z[u]);
     };
@@ -1430,9 +1432,12 @@ __device__ __forceinline__ float keep_if(float f, bool keep) { return keep ? f :
 template <typename T, typename Body>
 struct DirectVisit {
     Body &body;
-    T ER, abx, aby;
+    T ER, abx, aby, abz;
     T xa = 0, ya = 0, xb = 0, yb = 0, exy = 0, er = 0;
-    __device__ DirectVisit(Body &b, const PairRec &r) : body(b), ER((T)r.ER), abx((T)r.AB[0]), aby((T)r.AB[1]) {}
+    __device__ DirectVisit(Body &b, const PairRec &r)
+        : body(b), ER((T)r.ER), abx((T)r.AB[0]), aby((T)r.AB[1]), abz((T)r.AB[2])
+    {
+    }
     // ok = false: a lane without a row, every point cut
     __device__ __forceinline__ void row(const PtXY<T> &X, const PtXY<T> &Y, bool ok)
     {
@@ -1446,7 +1451,7 @@ struct DirectVisit {
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T E = exy * Z.e;
-        body(keep_if(v * E, E >= er), xa, ya, Z.a, xb, yb, Z.b);
+        body(keep_if(v * E, E >= er), xa, ya, Z.a, xb, yb, Z.a + abz);
     }
     __device__ __forceinline__ void done() {}
 };
@@ -1498,20 +1503,17 @@ struct TensorVisit {
         exy = X.e * Y.e;
         thr = ok ? ER / exy : T(__builtin_huge_val());
     }
-    // Z.b, Z.c hold (z - A_z)^2 and (z - A_z)^3
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T f = keep_if(v * Z.e, Z.e >= thr);
         W[0] += f;
-        if constexpr (L >= 1) W[1] += f * Z.a;
-        if constexpr (L >= 2) W[2] += f * Z.b;
-        if constexpr (L >= 3) W[3] += f * Z.c;
-        if constexpr (L >= 4) {
-            T p = Z.c;
+        if constexpr (L >= 1) {
+            T p = f * Z.a;   // f (z - A_z)^(lz - 1) for the next lz
+            W[1] += p;
 #pragma unroll
-            for (int lz = 4; lz <= L; ++lz) {
-                p *= Z.a;
-                W[lz] += f * p;
+            for (int lz = 2; lz <= L; ++lz) {
+                W[lz] += p * Z.a;
+                if (lz < L) p *= Z.a;
             }
         }
     }
@@ -1578,21 +1580,19 @@ struct TensorVisitTri {
         crow = gxz2 * dx + gyz2 * dy;
         r2 = ok ? R2 : T(-1);
     }
-    // Z.e: z offset from P; Z.a, Z.b, Z.c: (z - A_z), its square and cube
+    // Z.e: z offset from P; Z.a: z - A_z
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
         const T q = qrow + Z.e * (gzz * Z.e + crow);
         const T f = keep_if(v * texp<T>(nap * q), q <= r2);
         W[0] += f;
-        if constexpr (L >= 1) W[1] += f * Z.a;
-        if constexpr (L >= 2) W[2] += f * Z.b;
-        if constexpr (L >= 3) W[3] += f * Z.c;
-        if constexpr (L >= 4) {
-            T p = Z.c;
+        if constexpr (L >= 1) {
+            T p = f * Z.a;   // f (z - A_z)^(lz - 1) for the next lz
+            W[1] += p;
 #pragma unroll
-            for (int lz = 4; lz <= L; ++lz) {
-                p *= Z.a;
-                W[lz] += f * p;
+            for (int lz = 2; lz <= L; ++lz) {
+                W[lz] += p * Z.a;
+                if (lz < L) p *= Z.a;
             }
         }
     }
@@ -1658,8 +1658,8 @@ __host__ __device__ constexpr int row_capacity(int emax)
     return emax * emax <= kRowCap ? emax * emax : (kRowCap > emax ? kRowCap : emax);
 }
 
-// LDS layout of the pair-major kernels: the z point table tz[8 emax] (its
-// second half padding), the x and y point tables txy[2][4 emax], the block
+// LDS layout of the pair-major kernels: the z point table tz[2 kZSlots emax]
+// (its second half padding), the x and y point tables txy[2][4 emax], the block
 // lists bl[3][emax], their counts, the run-length counters hist[emax + 1],
 // and the block rows and their unsorted copy (row_capacity(emax) each).
 template <typename T>
@@ -1674,7 +1674,7 @@ template <typename T>
 struct PairSmem {
     static __host__ __device__ size_t table_bytes(int emax)
     {
-        const size_t b = (8 * sizeof(PtXY<T>) + 8 * sizeof(PtZ<T>)) * (size_t)emax;
+        const size_t b = (8 * sizeof(PtXY<T>) + 2 * kZSlots * sizeof(PtZ<T>)) * (size_t)emax;
         return (b + 15) & ~size_t(15);
     }
     static __host__ __device__ size_t hist_ints(int emax) { return ((size_t)emax + 1 + 3) & ~size_t(3); }
@@ -1682,7 +1682,7 @@ struct PairSmem {
     {
         PairLds<T> l;
         l.tz = reinterpret_cast<PtZ<T> *>(raw);
-        l.txy = reinterpret_cast<PtXY<T> *>(l.tz + 8 * emax);
+        l.txy = reinterpret_cast<PtXY<T> *>(l.tz + 2 * kZSlots * emax);
         l.bl = reinterpret_cast<AxisBlock *>(raw + table_bytes(emax));
         l.cnt = reinterpret_cast<int *>(l.bl + 3 * emax);
         l.hist = l.cnt + 4;
