@@ -706,6 +706,17 @@ __device__ __forceinline__ void horner_y_all(const T *cyz, T ya, T *cz, std::int
     ((cz[Z] = horner_y<L, Z, T>(cyz, ya, std::make_integer_sequence<int, L - Z>{})), ...);
 }
 
+// f where keep holds, else a value of magnitude below 2^-1022 (FP64: the
+// high word cleared, one select instead of two; FP32: 0).  Accumulated over
+// at most the points of a pair image or a block list, such values stay below 1e-300.
+__device__ __forceinline__ double keep_if(double f, bool keep)
+{
+    const long long b = __double_as_longlong(f);
+    const int hi = keep ? (int)(b >> 32) : 0;
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)(b & 0xffffffffLL));
+}
+__device__ __forceinline__ float keep_if(float f, bool keep) { return keep ? f : 0.0f; }
+
 // Density contributions of one lane's pair image to NX x-slices (x points
 // tx0 .. tx0 + NX - 1) of a block: rho(r) += E(r) sum_k Ct_k (r-A)^k with
 // the envelope E = fx fy fz cut at ER.  The polynomial is evaluated by
@@ -777,7 +788,7 @@ __device__ __forceinline__ void rho_points(const T *Ct, double xa0, double ya0, 
 #pragma unroll
                 for (int tz = 0; tz < 4; ++tz) q[tz] = q[tz] * zat[tz] + cz[lz];
 #pragma unroll
-            for (int tz = 0; tz < 4; ++tz) acc[ix * 16 + ty * 4 + tz] += ((E[tz] >= ER) ? E[tz] : T(0)) * q[tz];
+            for (int tz = 0; tz < 4; ++tz) acc[ix * 16 + ty * 4 + tz] += keep_if(E[tz], E[tz] >= ER) * q[tz];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -807,7 +818,7 @@ __device__ __forceinline__ void rho_points_direct(const T *Dk, double xa0, doubl
                 const T za = (T)(za0 + tz * G.h[2]);
                 const T zb = za + abz;
                 T E = exy * (T)fz[tz];
-                E = (E >= ER) ? E : T(0);
+                E = keep_if(E, E >= ER);
                 T a[NA], bb[NB];
                 monomials<LA, T>(xa, ya, za, a);
                 monomials<LB, T>(xb, yb, zb, bb);
@@ -1155,8 +1166,7 @@ __device__ __forceinline__ double uni(double v)
 
 // 1-D point tables of a pair image, at point 4 e + t of an axis (point t of
 // block list entry e): the envelope factor exp(-alpha_p (x - P)^2) and the
-// offset x - A; along z two more values: for the direct form z - B and 0,
-// for the moment form (z - A)^2 and (z - A)^3.
+// offset x - A.
 template <typename T> struct alignas(2 * sizeof(T)) PtXY { T e, a; };
 template <typename T> struct alignas(2 * sizeof(T)) PtZ { T e, a; };
 constexpr int kZSlots = 5;   // z table slots per block entry (4 points, 1 unused)
@@ -1414,17 +1424,6 @@ __device__ __forceinline__ void for_each_point(const PtXY<T> *txy, const PtZ<T> 
     }
     vis.done();
 }
-
-// f where keep holds, else a value of magnitude below 2^-1022 (FP64: the
-// high word cleared, one select instead of two; FP32: 0).  Accumulated over
-// at most a pair image's points, such values stay below 1e-300.
-__device__ __forceinline__ double keep_if(double f, bool keep)
-{
-    const long long b = __double_as_longlong(f);
-    const int hi = keep ? (int)(b >> 32) : 0;
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)(b & 0xffffffffLL));
-}
-__device__ __forceinline__ float keep_if(float f, bool keep) { return keep ? f : 0.0f; }
 
 // Visitor of the direct form: body(f, xa, ya, za, xb, yb, zb) per point with
 // f = v(r) exp(-alpha_p |r-P|^2) inside the sphere, else 0, (xa, ya, za) =
