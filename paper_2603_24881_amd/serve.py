@@ -185,7 +185,10 @@ class Scheduler:
                         self.ex.end(r)
                         self._release(r)
                     del busy[lane]
-            self._admit(pending, queue, self.ex.now() - t0)
+            # one reading of the clock for admission and for the idle test
+            # below: a request that arrives in between waits for the next trip
+            now = self.ex.now() - t0
+            self._admit(pending, queue, now)
             launched = False
             # the most restricted free lanes choose first
             free = sorted((lane for lane in range(self.lanes) if lane not in busy), key=self._limit)
@@ -208,7 +211,6 @@ class Scheduler:
                 launched = True
             if launched:
                 continue
-            now = self.ex.now() - t0
             t_next = t0 + pending[0].arrival if pending and pending[0].arrival > now else None
             if not busy and t_next is None:
                 if pending and not queue:

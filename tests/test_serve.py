@@ -129,6 +129,29 @@ def test_every_request_runs_in_exactly_one_round():
     assert sum(s.rounds) == len(reqs) and max(s.rounds) > 1
 
 
+class TickingExecutor(FakeExecutor):
+    """A host clock that moves on by itself: every reading is 0.3 ms later."""
+
+    def now(self):
+        self.t += 3e-4
+        return self.t
+
+
+@pytest.mark.parametrize("gap_ms", [2.75, 2.95, 3.05, 3.15, 3.35])
+def test_arrival_between_clock_readings_of_an_idle_server(gap_ms):
+    """A request that arrives after the server, idle again once a 2 ms round
+    ends, has read the clock for admission but before it reads it again to
+    decide whether to wait, is admitted on the next trip (no accounting
+    error).  With clock readings 0.3 ms apart, the gaps of 2.95 to 3.15 ms put
+    the arrival of the second request between the two readings."""
+    ex = TickingExecutor({"a": 10}, {"a": 1})
+    s = _sched(ex, 1000)
+    reqs = [Request(0, FOCK, "a", 0.0), Request(1, FOCK, "a", gap_ms * 1e-3)]
+    s.run(reqs)
+    assert all(r.error is None and r.done >= r.admitted >= r.arrival for r in reqs)
+    assert s.rounds == [1, 1]
+
+
 def test_lone_request_is_one_round_on_a_free_lane():
     ex = FakeExecutor({"a": 10}, {"a": 1})
     s = _sched(ex, 1000)
