@@ -347,7 +347,7 @@ def _flop_model(op, c, inc):
     L = la + lb
     na, nb = (la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2
     f1 = 2 * na * nb + 2 * (na + nb) + 4
-    tensor_rho = la == 2 or (la == 3 and 1 <= lb <= 2) or (la == 4 and lb >= 1)
+    tensor_rho = la == 2 or la == 3 or (la == 4 and lb >= 1)
     ft = 8 * (L + 2) * (L + 1) * L / 6 + 32 * (L + 1) * L / 2 + 16 + 64 * (2 * L + 3)
     if op == "rho":
         return (ft if tensor_rho else 64 * f1) * inc, 64 * f1 * inc

@@ -43,7 +43,7 @@ __host__ __device__ constexpr int ntab(int L) { return (L + 1) * (L + 2) * (L + 
 // the 256-water system.
 __host__ __device__ constexpr bool rho_tensor(int la, int lb)
 {
-    return la == 2 || (la == 3 && lb >= 1 && lb <= 2) || (la == 4 && lb >= 1);
+    return la == 2 || la == 3 || (la == 4 && lb >= 1);
 }
 // Whether the mat kernel of class (la, lb) accumulates the potential moments
 // of the monomials of r - A one axis at a time and forms the matrix elements

@@ -155,8 +155,8 @@ def test_fp32_variant_error_is_bounded():
 def test_flop_model_follows_its_definition():
     """The plan's work counts, per (l_a, l_b) class over all ten classes: the
     counting convention (direct evaluation, 64 points per block incidence),
-    the kernels' arithmetic (coefficient tensor for the rho d and f classes
-    except (f|s), (f|f); moments for mat with l_a + l_b >= 2) and the
+    the kernels' arithmetic (coefficient tensor for the rho d and f classes;
+    moments for mat with l_a + l_b >= 2) and the
     in-sphere count below the block count."""
     from math import comb
     from paper_2603_24881_amd.gpw import GPW
@@ -172,7 +172,7 @@ def test_flop_model_follows_its_definition():
             na, nb, L = (la + 1) * (la + 2) // 2, (lb + 1) * (lb + 2) // 2, la + lb
             f1 = 2 * na * nb + 2 * (na + nb) + 4
             conv += 64.0 * f1 * inc
-            tensor_rho = la == 2 or (la == 3 and 1 <= lb <= 2)
+            tensor_rho = la >= 2
             exec_rho += (8 * comb(L + 2, 3) + 32 * comb(L + 1, 2) + 16 + 64 * (2 * L + 3) if tensor_rho
                          else 64 * f1) * inc
             exec_mat += 64.0 * ((2 * L + 3) if L >= 2 else f1) * inc
