@@ -750,9 +750,10 @@ hipError_t build_partition(gpw_plan_s *pl, const PartitionInput &in, hipStream_t
         // coefficients at 4 x points (C(L+2,3) FMAs each), in y for the z
         // coefficients of 16 columns (C(L+1,2) FMAs each), 16 column envelope
         // products, per point L Horner FMAs, the envelope product and the
-        // accumulation.  mat through the moments: per point the envelope
-        // product, the cut potential, L powers and L+1 accumulations (the
-        // per-row and per-x-slice flushes, ~1-2 %, are not counted).
+        // accumulation.  mat through the moments: per point about 2L + 3
+        // flops (the cut potential v e_z, the powers of z - A_z, the L + 1
+        // accumulations; the flushes once per group of rows, ~1-2 %, are not
+        // counted).
         const double ft = 8.0 * (L + 2) * (L + 1) * L / 6.0 + 32.0 * (L + 1) * L / 2.0 + 16.0 + 64.0 * (2 * L + 3);
         I.flops_rho_exec += rho_tensor(la, lb) ? ft * (double)ninc : f1 * blkpts;
         I.flops_mat_exec += (mat_tensor(la, lb) ? 2.0 * L + 3.0 : f1) * blkpts;
