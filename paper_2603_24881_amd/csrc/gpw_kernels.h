@@ -717,6 +717,21 @@ __device__ __forceinline__ double keep_if(double f, bool keep)
 }
 __device__ __forceinline__ float keep_if(float f, bool keep) { return keep ? f : 0.0f; }
 
+// 1 / x from the hardware reciprocal and Newton steps r' = r + r (1 - x r)
+// (two in FP64, one in FP32): a few ulps, in place of a full division.  x = 0
+// gives NaN, which compares false.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+
 // Density contributions of one lane's pair image to NX x-slices (x points
 // tx0 .. tx0 + NX - 1) of a block: rho(r) += E(r) sum_k Ct_k (r-A)^k with
 // the envelope E = fx fy fz cut at ER.  The polynomial is evaluated by
@@ -1493,14 +1508,15 @@ struct TensorVisit {
         for (int k = 0; k <= L; ++k) W[k] = T(0);
     }
     // ok = false: a lane without a row, every point cut.  The cut
-    // ex ey ez >= E_R is taken as ez >= E_R / (ex ey) (+inf: none kept).
+    // ex ey ez >= E_R is taken as ez >= E_R / (ex ey) (+inf or NaN: none
+    // kept).
     __device__ __forceinline__ void row(const PtXY<T> &X, const PtXY<T> &Y, bool ok)
     {
         flush();
         xa = X.a;
         ya = Y.a;
         exy = X.e * Y.e;
-        thr = ok ? ER / exy : T(__builtin_huge_val());
+        thr = ok ? ER * recip(exy) : T(__builtin_huge_val());
     }
     __device__ __forceinline__ void point(T v, const PtZ<T> &Z)
     {
