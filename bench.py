@@ -251,7 +251,7 @@ def serving(n, rates, budget_gb):
     reg = time.perf_counter() - t0
     log(f"[bench] serving: 12 plans registered in {reg:.1f} s")
     out = {"requests": n, "sizes_waters": list(sizes), "geometries": 2, "grad_fraction": 0.5,
-           "budget_gb": budget_gb, "max_active": 32, "max_batch": 16, "lanes": ex.n_lanes,
+           "budget_gb": budget_gb, "max_active": 32, "max_batch": 16, "lanes": ex.n_lanes, "heavy_alone": True,
            "plan_register_s": round(reg, 2), "runs": []}
     warm = poisson_trace(24, 1000.0, seed=1999)
     Scheduler(ex, budget_gb * 2 ** 30).run(warm)

@@ -85,12 +85,16 @@ def system_key(n_waters, geometry):
 
 
 class Scheduler:
-    def __init__(self, executor, budget_bytes, max_active=32, max_batch=16, group_ratio=2.0):
+    def __init__(self, executor, budget_bytes, max_active=32, max_batch=16, group_ratio=2.0, heavy_alone=True):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.max_batch = int(max_batch)
         self.group_ratio = group_ratio
+        # heavy_alone: a request too heavy for every restricted lane runs in a
+        # round of its own (batching gains it nothing: its kernels fill the
+        # device; a second heavy request in its round only delays it)
+        self.heavy_alone = bool(heavy_alone)
         self.lanes = int(executor.n_lanes)
         self.used = 0
         self.n_active = 0                 # admitted, not yet done
@@ -154,6 +158,10 @@ class Scheduler:
         lim = self.ex.lane_limit(lane)
         return math.inf if lim is None else lim
 
+    def _light_limit(self):
+        """The largest work estimate that a restricted lane takes (inf: none)."""
+        return min(self._limit(lane) for lane in range(self.lanes))
+
     def _group(self, queue, limit=math.inf):
         """The waiting requests that may share a round on a lane that takes
         work estimates up to limit: the oldest eligible one and those whose
@@ -202,6 +210,8 @@ class Scheduler:
                 c = self.ex.cost(group[0].system)
                 n_free = sum(1 for x in free if x not in busy and self._limit(x) >= c)
                 k = min(self.max_batch, -(-len(group) // max(1, n_free)))
+                if self.heavy_alone and c > self._light_limit():
+                    k = 1
                 batch = group[:k]
                 for r in batch:
                     queue.remove(r)

@@ -320,3 +320,27 @@ def test_poisson_trace_statistics():
     sizes = {r.system.split("g")[0] for r in tr}
     assert sizes == {"w8", "w16", "w32", "w64", "w128", "w256"}
     assert poisson_trace(50, 20.0)[7].arrival == poisson_trace(50, 20.0)[7].arrival
+
+
+def _heavy_light_run(heavy_alone):
+    ex = FakeExecutor({"h": 10, "l": 1}, {"h": 1, "l": 1}, cost={"h": 5e-3, "l": 1e-4}, lanes=2, limits={1: 1e-3})
+    s = Scheduler(ex, 1000, heavy_alone=heavy_alone)
+    ex.sched = s
+    reqs = [Request(i, FOCK, "h", 0.0) for i in range(3)] + [Request(3 + i, FOCK, "l", 0.0) for i in range(4)]
+    s.run(reqs)
+    assert all(r.error is None for r in reqs)
+    heavy = [e for e in _launches(ex) if any(reqs[q].system == "h" for q in e[2])]
+    light = [e for e in _launches(ex) if all(reqs[q].system == "l" for q in e[2])]
+    return heavy, light, reqs
+
+
+def test_heavy_requests_run_in_rounds_of_their_own():
+    """A request too heavy for the restricted lane is not batched with
+    another (it would only wait for it); light requests still share rounds."""
+    heavy, light, reqs = _heavy_light_run(True)
+    assert len(heavy) == 3 and all(len(e[2]) == 1 for e in heavy)
+    assert max(len(e[2]) for e in light) > 1
+    first = min(reqs[:3], key=lambda r: r.done)
+    heavy2, _, reqs2 = _heavy_light_run(False)
+    assert any(len(e[2]) > 1 for e in heavy2)
+    assert first.done < min(r.done for r in reqs2[:3])   # the first heavy request completes sooner
